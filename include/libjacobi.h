@@ -1,0 +1,209 @@
+/*
+ * libjacobi -- partitioned synchronous Jacobi on AMD MI355X (gfx950).
+ *
+ * C ABI.  Every function returns a jac_status (no exception crosses the ABI);
+ * jac_last_error() gives a thread-local message for the last failure.
+ *
+ * The method (Cheik Ahamed & Magoules, "On the stability and performance of
+ * the solution of sparse linear systems by partitioned procedures"):
+ *   split A = D - (-(L+U)) with D the diagonal (section 3, splitting and
+ *   Jacobi equations) and iterate the correction form
+ *       x_{k+1} = x_k + D^{-1} (b - A x_k)
+ *   (section 3, second form of the Jacobi iteration), with D^{-1} formed
+ *   once and, per sweep, q = A x_k, r = b - q, a norm of r, a stop test and
+ *   the update (section 3, algorithm "Jacobi method: vectorial version").
+ *   The matrix is split into partitions by naive band rows, by band rows with
+ *   sparsity-pattern dependency lists, or by substructuring with the interface
+ *   unknowns ordered last (section 4).
+ *
+ * Conventions
+ *   - Indices are int32, 0-based unless index_base = 1 is given at creation
+ *     (the 1-based AA/JA/IA arrays of the paper's CSR figure, section 4.1).
+ *   - "_host" pointers are host memory; "_dev" pointers are device memory on
+ *     the handle's device.  Device pointers are borrowed for the duration of
+ *     the call only and all device work is ordered on the handle's stream.
+ *   - Vectors with several right-hand sides are n x nrhs column-major
+ *     (right-hand side c occupies entries [c*n, (c+1)*n)), in the caller's
+ *     original row order whatever the partition.
+ *   - The library owns every internal device buffer and frees it in
+ *     jac_destroy.  Host arrays passed in are copied; the caller keeps them.
+ *   - Synchronous semantics: every component of x_{k+1} is computed from x_k
+ *     (two buffers, never in place).
+ *   - One handle must not be used by two threads at once.  The library has
+ *     no other mutable global state except the autotuner's cache (guarded).
+ */
+#ifndef LIBJACOBI_H
+#define LIBJACOBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jac_s *jac_handle;
+
+typedef enum {
+    JAC_OK = 0,
+    JAC_NOT_CONVERGED = 1,   /* soft: outputs are valid (x_maxit and its residual) */
+    JAC_E_INVALID = -1,      /* bad argument or malformed CSR                      */
+    JAC_E_ZERO_DIAG = -2,    /* a row lacks its diagonal or the diagonal is 0      */
+    JAC_E_NOMEM = -3,        /* host or device allocation failed                   */
+    JAC_E_HIP = -4,          /* HIP runtime error; the handle may be unusable      */
+    JAC_E_STATE = -5,        /* call made in the wrong order                       */
+    JAC_E_DIVERGED = -6      /* residual norm non-finite or beyond 1e150*max(|b|,1) */
+} jac_status;
+
+typedef enum {
+    JAC_BANDROW = 1,         /* naive band rows: tiles read x straight from memory  */
+    JAC_BANDROW_SP = 2,      /* band rows + sparsity-pattern lists: x staged in LDS */
+    JAC_SUBSTRUCT = 3        /* interiors first, interface last: x staged in LDS    */
+} jac_mode;
+
+typedef enum {
+    JAC_NORM_L2_REL = 0,     /* ||b - A x_k||_2 / ||b||_2 (absolute when ||b|| = 0) */
+    JAC_NORM_INF_ABS = 1     /* max_i |b - A x_k|_i, the paper's experimental test
+                                (section 6: infinity norm of D(x_{k+1}-x_k), which
+                                equals the residual's infinity norm)               */
+} jac_norm;
+
+typedef enum {
+    JAC_FP64 = 0,            /* every sweep in FP64                                 */
+    JAC_FP32_REFINE = 1      /* FP32 inner sweeps on A d = r, FP64 outer residual,
+                                norm and update x += d                              */
+} jac_prec;
+
+/* Tunables (jac_set_option / jac_get_option). */
+typedef enum {
+    JAC_OPT_TILE_ROWS = 1,   /* max rows per tile (multiple of 64), default 1024    */
+    JAC_OPT_BLOCK = 2,       /* threads per workgroup: 64..512, multiple of 64       */
+    JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096   */
+    JAC_OPT_LOOP = 4,        /* 0 = persistent device loop, 1 = one launch per sweep */
+    JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU (0 = occupancy)  */
+    JAC_OPT_INNER_TOL = 6,   /* FP32 refinement: inner relative residual, x1e-9     */
+    JAC_OPT_INNER_MAX = 7,   /* FP32 refinement: max inner sweeps per outer step    */
+    JAC_OPT_CKPT_MEM_MB = 8  /* adjoint: cap on segment buffers (MiB)               */
+} jac_option;
+
+typedef struct {
+    int32_t n, nrhs, nparts, mode;
+    int64_t nnz;
+    int64_t ell_slots;           /* stored slots incl. padding (sliced layout)      */
+    int32_t ntiles, nslices;
+    int32_t max_footprint;       /* largest staged x footprint of a tile (entries)  */
+    int32_t col_bytes;           /* 4 = global int32 columns, 2 = tile-local u16    */
+    int64_t halo_entries;        /* sum of the receive lists                        */
+    int64_t staged_entries;      /* sum over tiles of staged x entries             */
+    int64_t alg_bytes_per_sweep; /* 12 nnz + 4 (n+1) + 32 n per right-hand side... */
+    int64_t dev_bytes_per_sweep; /* bytes the kernel actually streams per sweep     */
+    int32_t loop_grid;           /* workgroups of the persistent loop               */
+    int32_t block;               /* threads per workgroup                           */
+} jac_info;
+
+/* Create a system from host CSR arrays (row_ptr[n+1], col_idx[nnz],
+ * vals[nnz]) and nrhs right-hand sides b (n x nrhs, column-major, host).
+ * Columns must be strictly ascending within each row and every diagonal must
+ * be present and nonzero (JAC_E_ZERO_DIAG), otherwise JAC_E_INVALID.
+ * hip_stream: the hipStream_t all device work is ordered on (NULL = default).
+ * D^{-1} is formed once here, one rounding per entry (section 3, vectorial
+ * algorithm).  The new handle has x = 0 and an implicit JAC_BANDROW split
+ * into one part.  nrhs must be 1, 2 or 4. */
+jac_status jac_create(int32_t n, const int32_t *row_ptr_host, const int32_t *col_idx_host,
+                      const double *vals_host, int32_t nrhs, const double *b_host, int32_t index_base,
+                      void *hip_stream, jac_handle *out);
+
+/* New coefficients on the same pattern, in the caller's CSR entry order,
+ * from device memory (vals_dev[nnz]); D^{-1} is recomputed.  A zero diagonal
+ * gives JAC_E_ZERO_DIAG and leaves the old values in place. */
+jac_status jac_set_values(jac_handle h, const double *vals_dev);
+
+/* New right-hand sides from device memory (n x nrhs column-major). */
+jac_status jac_set_rhs(jac_handle h, const double *b_dev);
+
+/* Optional geometry for JAC_SUBSTRUCT: rows are the nodes of an nx*ny*nz
+ * grid, x fastest (row = i + nx*(j + ny*k)).  Without it, subdomains are
+ * contiguous row blocks. */
+jac_status jac_set_grid(jac_handle h, int32_t nx, int32_t ny, int32_t nz);
+
+/* Split the matrix into nparts parts (section 4).  Band boundaries are
+ * floor(p*n/nparts) (section 4.2).  For JAC_SUBSTRUCT, sub_grid = {sx,sy,sz}
+ * gives sx*sy*sz subdomains (NULL: nparts contiguous subdomains, one per
+ * part), grouped into parts by the same floor rule; a node is interface iff
+ * a neighbour in A or A^T lies in another subdomain; the new order is the
+ * interiors of each subdomain (ascending original index) then the interface
+ * sorted by (subdomain, index) (section 4.3, block form with interface last).
+ * Rebuilds the device layout and resets x to the current x in the new order. */
+jac_status jac_partition(jac_handle h, jac_mode mode, int32_t nparts, const int32_t *sub_grid_host);
+
+/* Host copies of the split, for inspection and parity checks.  Any output
+ * may be NULL.  perm[n]: new -> original row.  bounds[*nbounds]: band
+ * boundaries (nparts+1) for band-row modes; for JAC_SUBSTRUCT the
+ * concatenation sub_int_ptr[S+1], sub_ifc_ptr[S+1], part_sub_ptr[nparts+1].
+ * recv_ptr[nparts+1], recv_idx[*nrecv]: receive lists in the new numbering,
+ * grouped by owner part ascending and ascending within a group (the
+ * dependency lists of section 4.2.2; interface values for section 4.3; empty
+ * for the naive split).  On entry *nbounds and *nrecv give the capacity of
+ * bounds and recv_idx (ignored when those are NULL); on return they hold the
+ * sizes. */
+jac_status jac_get_partition(jac_handle h, int32_t *perm_host, int32_t *bounds_host, int32_t *nbounds,
+                             int32_t *recv_ptr_host, int32_t *recv_idx_host, int64_t *nrecv);
+
+/* Set x (n x nrhs, original order, device) or zero it (x_dev = NULL). */
+jac_status jac_set_x(jac_handle h, const double *x_dev);
+
+/* Copy the current x (n x nrhs, original order) to x_dev. */
+jac_status jac_get_x(jac_handle h, double *x_dev);
+
+/* nsweeps synchronous sweeps from the current x, with no stop test.
+ * hist_dev (nullable, nsweeps*nrhs doubles, sweep-major) receives
+ * ||b - A x_k||_2 for each right-hand side of every sweep k (the residual of
+ * the iterate each sweep starts from). */
+jac_status jac_sweep(jac_handle h, int32_t nsweeps, double *hist_dev);
+
+/* Solve from the current x with the vectorial algorithm's test (section 3):
+ * for k = 0, 1, ...: evaluate r_k; stop with x_k when its norm passes
+ * (norm <= tol); at k == maxit return x_maxit and JAC_NOT_CONVERGED.  Each
+ * right-hand side stops on its own and is frozen from then on.
+ * sweeps_out[nrhs] = updates applied (the paper's count is sweeps + 1),
+ * relres_out[nrhs] = the norm of the returned iterate (relative for
+ * JAC_NORM_L2_REL).  Both outputs are host arrays and may be NULL.
+ * prec = JAC_FP32_REFINE runs FP32 inner sweeps with FP64 refinement; then
+ * sweeps_out counts inner FP32 sweeps and the norm is always the FP64 one. */
+jac_status jac_solve(jac_handle h, double tol, int32_t maxit, jac_norm norm, jac_prec prec,
+                     int32_t *sweeps_out, double *relres_out);
+
+/* Solve nsys independent systems in one persistent launch (every system is
+ * swept in lockstep; each (system, right-hand side) column stops on its own
+ * relative 2-norm test and is frozen; a system with every column stopped
+ * leaves the work list).  All handles must share the device and stream of
+ * hs[0] and have their partition done; outputs are host arrays indexed
+ * [s*4 + c] up to each handle's nrhs (stride 4).  Results equal nsys
+ * separate jac_solve calls with JAC_NORM_L2_REL and JAC_FP64. */
+jac_status jac_solve_batched(const jac_handle *hs, int32_t nsys, double tol, int32_t maxit,
+                             int32_t *sweeps_out_host, double *relres_out_host);
+
+/* Reverse-mode derivative of K sweeps from x_0 = 0 for right-hand side 0:
+ * given gx_dev = dL/dx_K (n, original order), writes gb_dev = dL/db (n) and
+ * gvals_dev = dL/dvals (nnz, caller's CSR entry order, diagonal included).
+ * Iterates are checkpointed every ckpt_every sweeps and recomputed per
+ * segment.  Leaves x = x_K in the handle.  Either output may be NULL. */
+jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double *gx_dev, double *gb_dev,
+                       double *gvals_dev);
+
+/* Time candidate tile shapes and loop settings on this handle and keep the
+ * fastest (x is restored afterwards).  The choice is cached on disk under
+ * $JAC_TUNE_CACHE (if set), keyed by the matrix shape and split. */
+jac_status jac_autotune(jac_handle h, int32_t sweeps_per_trial);
+
+jac_status jac_set_option(jac_handle h, jac_option opt, int64_t value);
+jac_status jac_get_option(jac_handle h, jac_option opt, int64_t *value);
+jac_status jac_get_info(jac_handle h, jac_info *info);
+
+void jac_destroy(jac_handle h);
+const char *jac_status_string(jac_status s);
+const char *jac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBJACOBI_H */

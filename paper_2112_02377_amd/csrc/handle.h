@@ -1,0 +1,93 @@
+// The handle behind jac_handle and the host helpers shared by the ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "jac_internal.h"
+#include "kernels.h"
+
+namespace jac {
+
+// Owned device allocation.
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem();
+    void reset();
+    void* alloc(size_t nb);
+};
+
+struct Options {
+    int32_t tile_rows = 1024;
+    int32_t block = 256;
+    int32_t lds_elems = 4096;
+    int32_t loop = 0;          // 0 persistent, 1 launch per sweep
+    int32_t wg_per_cu = 0;
+    double inner_tol = 1e-5;
+    int32_t inner_max = 256;
+    int64_t ckpt_mb = 4096;
+};
+
+struct DeviceArrays {
+    DevMem tile_row0, tile_slice0, slice_row0, slice_width, slice_off;
+    DevMem col32, col16, tile_run0, run_start, run_lds, tile_fp, tile_own;
+    DevMem slot_of_caller, diag_slot, perm;
+    DevMem vals_caller, b_caller;          // caller order, kept for re-planning
+    DevMem val, val32, invd, invd32;
+    DevMem b, x0, x1, tile_part, tile_base;
+    DevMem sys, state, bar, bad, norm_part, bnorm;
+    DevMem batch_sys, batch_state, batch_tile_base;
+    // FP32 refinement
+    DevMem r32, d0, d1, rpart;
+    // adjoint
+    DevMem t_rp, t_ci, t_map;
+};
+
+struct Handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Csr a;                      // caller pattern, 0-based (values live on the device)
+    int32_t nrhs = 1;
+    int32_t grid[3] = {0, 0, 0};
+    bool has_grid = false;
+    bool planned = false;
+    Partition part;
+    Plan plan;
+    Options opt;
+    DeviceArrays d;
+    double bnorm[4] = {0, 0, 0, 0};
+    int last_grid = 0;
+    int last_status = 0;
+    // adjoint: plan of A^T (built on first use)
+    bool have_t = false;
+    Plan tplan;
+    DeviceArrays td;
+
+    void sync();
+    void replan(int mode, int32_t nparts, const int32_t* sub_grid);
+    void apply_values();
+    void ensure_fp32();
+    void update_bnorm();
+    void get_x_dev(double* out);
+    SysDev sysdev(bool fp32) const;
+    int lds_fp_bytes(bool fp32) const;
+    int lds_runs() const;
+};
+
+int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work);
+void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
+              DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
+              int fp_bytes, int runs, bool staged, int nrhs);
+jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t* sweeps_out, double* relres_out);
+void set_last_error(const std::string& m);
+
+}  // namespace jac
+
+struct jac_s : public jac::Handle {};

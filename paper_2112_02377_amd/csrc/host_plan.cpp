@@ -1,0 +1,174 @@
+// Tile planner: cuts the permuted matrix into tiles (contiguous row ranges
+// that never straddle a partition or subdomain boundary), each tile into
+// 64-row slices stored column-major and padded to the slice's longest row,
+// and -- for the staged modes -- lists the x entries each tile references
+// (its footprint) as runs of consecutive columns, with every column index
+// rewritten as a 16-bit offset into the tile's staged copy of x.
+//
+// The footprint is the single-device form of the paper's dependency lists
+// (section 4.2.2) and interface exchange (section 4.3): a tile reads from
+// memory exactly the x values its rows need, once, into LDS.
+#include <algorithm>
+#include <numeric>
+
+#include "jac_internal.h"
+
+namespace jac {
+
+namespace {
+
+struct Footprint {
+    std::vector<int32_t> cols;   // sorted unique columns
+    int32_t runs = 0;
+};
+
+void footprint(const Csr& a, int32_t r0, int32_t r1, Footprint& fp)
+{
+    fp.cols.assign(a.ci.begin() + a.rp[r0], a.ci.begin() + a.rp[r1]);
+    std::sort(fp.cols.begin(), fp.cols.end());
+    fp.cols.erase(std::unique(fp.cols.begin(), fp.cols.end()), fp.cols.end());
+    fp.runs = 0;
+    for (size_t m = 0; m < fp.cols.size(); ++m)
+        if (m == 0 || fp.cols[m] != fp.cols[m - 1] + 1) ++fp.runs;
+}
+
+}  // namespace
+
+Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanParams& prm_in)
+{
+    Plan pl;
+    pl.prm = prm_in;
+    PlanParams& prm = pl.prm;
+    if (prm.tile_rows < kSlice || prm.tile_rows % kSlice) fail(JAC_E_INVALID, "tile rows must be a multiple of 64");
+    if (prm.staged && (prm.lds_elems < kSlice || prm.lds_elems > 65536))
+        fail(JAC_E_INVALID, "staged footprint must be in [64, 65536]");
+    const int32_t n = a.n;
+    std::vector<int32_t> cuts = cuts_in;
+    cuts.push_back(0);
+    cuts.push_back(n);
+    std::sort(cuts.begin(), cuts.end());
+    cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+
+    // 1. tiles
+    Footprint fp;
+    std::vector<Footprint> fps;
+    pl.tile_row0.clear();
+    bool staged = prm.staged;
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+        int32_t r = cuts[c];
+        const int32_t seg_end = cuts[c + 1];
+        while (r < seg_end) {
+            int32_t e = std::min(seg_end, r + prm.tile_rows);
+            if (staged) {
+                for (;;) {
+                    footprint(a, r, e, fp);
+                    if ((int32_t)fp.cols.size() <= prm.lds_elems && fp.runs <= prm.max_runs) break;
+                    if (e - r <= kSlice) { staged = false; break; }
+                    int32_t half = ((e - r) / 2 + kSlice - 1) / kSlice * kSlice;
+                    e = r + std::max(kSlice, std::min(half, e - r - kSlice));
+                }
+                if (staged) fps.push_back(fp);
+            }
+            pl.tile_row0.push_back(r);
+            r = e;
+        }
+    }
+    pl.tile_row0.push_back(n);
+    pl.ntiles = (int32_t)pl.tile_row0.size() - 1;
+    if (!staged) { prm.staged = false; fps.clear(); }
+
+    // 2. slices and slot layout
+    pl.tile_slice0.assign((size_t)pl.ntiles + 1, 0);
+    pl.slice_row0.clear();
+    pl.slice_width.clear();
+    pl.slice_off.assign(1, 0);
+    for (int32_t t = 0; t < pl.ntiles; ++t) {
+        pl.tile_slice0[t] = (int32_t)pl.slice_row0.size();
+        for (int32_t r = pl.tile_row0[t]; r < pl.tile_row0[t + 1]; r += kSlice) {
+            const int32_t re = std::min(pl.tile_row0[t + 1], r + kSlice);
+            int32_t w = 0;
+            for (int32_t i = r; i < re; ++i) w = std::max(w, a.rp[i + 1] - a.rp[i]);
+            pl.slice_row0.push_back(r);
+            pl.slice_width.push_back(w);
+            pl.slice_off.push_back(pl.slice_off.back() + (int64_t)w * kSlice);
+        }
+    }
+    pl.tile_slice0[pl.ntiles] = (int32_t)pl.slice_row0.size();
+    pl.nslices = (int32_t)pl.slice_row0.size();
+    pl.slots = pl.slice_off.back();
+    if (pl.slots >= ((int64_t)1 << 31)) fail(JAC_E_INVALID, "matrix too large for 32-bit slot indices");
+
+    // 3. columns per slot, entry -> slot map, diagonal slots
+    pl.slot_of_nnz.assign(a.ci.size(), -1);
+    pl.diag_slot.assign((size_t)n, -1);
+    if (prm.staged) {
+        pl.col16.assign((size_t)pl.slots, 0);
+        pl.tile_run0.assign((size_t)pl.ntiles + 1, 0);
+        pl.tile_fp.assign((size_t)pl.ntiles, 0);
+        pl.tile_own.assign((size_t)pl.ntiles, 0);
+        pl.run_start.clear();
+        pl.run_lds.clear();
+    } else {
+        pl.col32.assign((size_t)pl.slots, 0);
+    }
+    pl.max_fp = 0;
+    pl.max_runs = 0;
+    pl.staged_entries = 0;
+    for (int32_t t = 0; t < pl.ntiles; ++t) {
+        const int32_t r0 = pl.tile_row0[t], r1 = pl.tile_row0[t + 1];
+        const std::vector<int32_t>* cols = nullptr;
+        int32_t own = 0;
+        if (prm.staged) {
+            cols = &fps[t].cols;
+            pl.tile_run0[t] = (int32_t)pl.run_start.size();
+            for (size_t m = 0; m < cols->size(); ++m)
+                if (m == 0 || (*cols)[m] != (*cols)[m - 1] + 1) {
+                    pl.run_start.push_back((*cols)[m]);
+                    pl.run_lds.push_back((int32_t)m);
+                }
+            pl.tile_fp[t] = (int32_t)cols->size();
+            own = (int32_t)(std::lower_bound(cols->begin(), cols->end(), r0) - cols->begin());
+            pl.tile_own[t] = own;
+            pl.max_fp = std::max(pl.max_fp, pl.tile_fp[t]);
+            pl.max_runs = std::max(pl.max_runs, (int32_t)pl.run_start.size() - pl.tile_run0[t]);
+            pl.staged_entries += pl.tile_fp[t];
+        }
+        for (int32_t s = pl.tile_slice0[t]; s < pl.tile_slice0[t + 1]; ++s) {
+            const int32_t row0 = pl.slice_row0[s];
+            const int32_t w = pl.slice_width[s];
+            const int64_t off = pl.slice_off[s];
+            for (int32_t lane = 0; lane < kSlice; ++lane) {
+                const int32_t i = row0 + lane;
+                const bool live = i < r1;
+                // padding slots point at a column the tile already holds
+                const int32_t pad_global = live ? i : r0;
+                const int32_t pad_local = live ? own + (i - r0) : own;
+                const int32_t len = live ? a.rp[i + 1] - a.rp[i] : 0;
+                for (int32_t k = 0; k < w; ++k) {
+                    const int64_t slot = off + (int64_t)k * kSlice + lane;
+                    if (k < len) {
+                        const int32_t p = a.rp[i] + k;
+                        const int32_t c = a.ci[p];
+                        pl.slot_of_nnz[p] = slot;
+                        if (c == i) pl.diag_slot[i] = slot;
+                        if (prm.staged) {
+                            const int32_t loc =
+                                (int32_t)(std::lower_bound(cols->begin(), cols->end(), c) - cols->begin());
+                            pl.col16[slot] = (uint16_t)loc;
+                        } else {
+                            pl.col32[slot] = c;
+                        }
+                    } else if (prm.staged) {
+                        pl.col16[slot] = (uint16_t)pad_local;
+                    } else {
+                        pl.col32[slot] = pad_global;
+                    }
+                }
+            }
+        }
+    }
+    if (prm.staged) pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+    return pl;
+}
+
+}  // namespace jac

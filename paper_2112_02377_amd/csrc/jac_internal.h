@@ -1,0 +1,91 @@
+// Internal declarations of libjacobi: host-side structures shared by the
+// partitioner, the tile planner, the C ABI and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/libjacobi.h"
+
+namespace jac {
+
+constexpr int kSlice = 64;          // rows per slice = one wavefront
+constexpr int kMaxRhs = 4;
+
+// Thrown inside the library, turned into a status at the ABI boundary.
+struct Error {
+    jac_status status;
+    std::string msg;
+};
+[[noreturn]] void fail(jac_status s, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define JAC_HIP(call) ::jac::hip_check((call), #call)
+
+// A 0-based CSR matrix on the host, columns strictly ascending per row.
+struct Csr {
+    int32_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;          // may be empty for pattern-only uses
+    int64_t nnz() const { return (int64_t)ci.size(); }
+};
+
+// Validate (and rebase) caller CSR; throws JAC_E_INVALID / JAC_E_ZERO_DIAG.
+Csr ingest_csr(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t index_base);
+
+// Result of a split (section 4).
+struct Partition {
+    int mode = JAC_BANDROW;
+    int32_t nparts = 1;
+    std::vector<int32_t> perm;      // new -> old
+    std::vector<int32_t> iperm;     // old -> new
+    std::vector<int32_t> bounds;    // see jac_get_partition
+    std::vector<int32_t> cuts;      // row indices (new order) tiles never straddle, ascending, 0 and n included
+    std::vector<int32_t> owner;     // part of each new row
+    std::vector<int32_t> recv_ptr;  // nparts + 1
+    std::vector<int32_t> recv_idx;  // new numbering
+    int32_t n_interior = -1;
+};
+
+Partition make_partition(const Csr& a, int mode, int32_t nparts, const int32_t* sub_grid, const int32_t* grid);
+
+// P A P^T with ascending columns; src[p] = index in a of new entry p.
+Csr permute(const Csr& a, const std::vector<int32_t>& perm, const std::vector<int32_t>& iperm,
+            std::vector<int64_t>* src);
+
+// Sliced tile layout built from the permuted CSR.
+struct PlanParams {
+    int32_t tile_rows = 1024;       // multiple of kSlice
+    int32_t lds_elems = 4096;       // max staged x entries per tile
+    int32_t max_runs = 1024;        // max footprint runs per tile
+    bool staged = false;            // stage x through LDS with 16-bit local columns
+};
+
+struct Plan {
+    PlanParams prm;
+    int32_t ntiles = 0, nslices = 0;
+    std::vector<int32_t> tile_row0;   // ntiles + 1
+    std::vector<int32_t> tile_slice0; // ntiles + 1
+    std::vector<int32_t> slice_row0;  // nslices
+    std::vector<int32_t> slice_width; // nslices
+    std::vector<int64_t> slice_off;   // nslices + 1 (slot offsets)
+    int64_t slots = 0;
+    std::vector<int32_t> col32;       // slots (global columns), when !staged
+    std::vector<uint16_t> col16;      // slots (tile-local columns), when staged
+    std::vector<int64_t> slot_of_nnz; // entry p of the permuted CSR -> slot
+    std::vector<int64_t> diag_slot;   // new row -> slot of its diagonal
+    // staging (staged only)
+    std::vector<int32_t> tile_run0;   // ntiles + 1
+    std::vector<int32_t> run_start;   // global column of each run
+    std::vector<int32_t> run_lds;     // LDS offset of each run (per tile, from 0)
+    std::vector<int32_t> tile_fp;     // footprint entries per tile
+    std::vector<int32_t> tile_own;    // LDS offset of the tile's own first row
+    int32_t max_fp = 0, max_runs = 0;
+    int64_t staged_entries = 0;
+};
+
+Plan make_plan(const Csr& pa, const std::vector<int32_t>& cuts, const PlanParams& prm);
+
+}  // namespace jac

@@ -1,0 +1,63 @@
+// Device-side structures shared by the kernels and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace jac {
+
+constexpr int32_t kRunning = 0x7fffffff;   // "not stopped" sweep marker
+
+// One system's device arrays (plain pointers; lives in device memory so a
+// batched launch can index many systems).
+struct SysDev {
+    const int32_t* tile_row0;
+    const int32_t* tile_slice0;
+    const int32_t* slice_row0;
+    const int32_t* slice_width;
+    const int64_t* slice_off;
+    const int32_t* col32;     // global columns (unstaged)
+    const uint16_t* col16;    // tile-local columns (staged)
+    const int32_t* tile_run0;
+    const int32_t* run_start;
+    const int32_t* run_lds;
+    const int32_t* tile_fp;
+    const int32_t* tile_own;
+    const void* val;          // slot values, T
+    const void* invd;         // D^{-1}, T
+    const void* b;            // right-hand sides, T, node-major [n][nrhs]
+    void* x0;                 // iterate buffers, T, node-major [n][nrhs]
+    void* x1;
+    double* tile_part;        // [ntiles][nrhs] per-tile norm partials
+    int32_t n, ntiles, nrhs, staged;
+    double thr[4];            // stop thresholds per right-hand side
+    double big[4];            // divergence thresholds per right-hand side
+};
+
+// Per-system control state.  Every "sweep" field holds kRunning until set,
+// and is only ever lowered from kRunning to a sweep index, so a reader racing
+// the writer within one sweep takes the same decision either way.
+struct SysState {
+    int32_t stop_k[4];        // column stopped on the residual of this sweep
+    int32_t done_k;           // system leaves the work list from this sweep on
+    int32_t status;           // JAC_OK, JAC_NOT_CONVERGED, JAC_E_DIVERGED
+    int32_t last_k;           // last sweep whose residual was reduced
+    uint32_t arrive;          // tiles finished in the current sweep
+    double nrm[4];            // norms of the last reduced residual
+};
+
+struct LoopParams {
+    const SysDev* sys;        // [nsys]
+    SysState* st;             // [nsys]
+    const int32_t* tile_base; // [nsys+1] prefix of tile counts (static)
+    double* hist;             // nullable, [(k - k0) * nrhs + c] of system 0
+    uint32_t* bar;            // [2] grid barrier: count, generation
+    int32_t nsys;
+    int32_t k0;               // first sweep
+    int32_t kend;             // fixed mode: sweeps k0..kend-1; solve mode: test up to kend (maxit)
+    int32_t solve;            // 1 = stop tests, 0 = fixed sweeps
+    int32_t norm_inf;         // 1 = max |r|, 0 = sum r^2
+};
+
+}  // namespace jac
