@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the synchronous Jacobi sweep on one MI355X.
+
+Workload (one "step"): the 128^3 7-point FP64 Laplacian (n = 2,097,152,
+nnz = 14,581,760, b = A x* with x* seeded uniform in [-1,1]) swept 2000 times
+from x0 = 0 under each of the three splits of the paper's section 4, 64 parts
+each: naive band rows (JB), band rows with sparsity-pattern lists (JBO), and
+substructuring on an 8x8x8 subdomain grid grouped into 64 parts (JSS), with the
+residual 2-norm of every sweep recorded on the device.
+
+value = algorithmic bytes of all sweeps of the timed steps / their time, with
+the CSR byte model 12 nnz + 4 (n+1) + 32 n per sweep (values, columns, row
+pointers, x, b, D^{-1}, x').  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "Jacobi sweep GB/s (% HBM peak) at 128^3 FP64; batched/adjoint/FP32 vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--sweeps", type=int, default=2000)
+    ap.add_argument("--modes", default="JB,JBO,JSS")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=60)
+    ap.add_argument("--loop", type=int, default=0, help="0 = one launch per sweep, 1 = persistent loop")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def src_digest():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2112_02377_amd", "csrc"))):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(ROOT, "paper_2112_02377_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_tag, launches_bytes):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, when it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    rec = t.get(kernel_tag)
+    if not rec or rec.get("src_digest") != src_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sysm, sweeps):
+    from oracle import ref
+    threads = min(16, os.cpu_count() or 1)
+    ref.sweeps(sysm.row_ptr, sysm.col_idx, sysm.vals, sysm.b[0], 2, threads=threads)
+    t0 = time.perf_counter()
+    ref.sweeps(sysm.row_ptr, sysm.col_idx, sysm.vals, sysm.b[0], sweeps, threads=threads)
+    dt = time.perf_counter() - t0
+    from paper_2112_02377_amd.workloads import bytes_per_sweep
+    return {"value": round(sweeps * bytes_per_sweep(sysm.n, sysm.nnz) / dt / 1e9, 3), "unit": "GB/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{sweeps} sweeps of the same {round(sysm.n ** (1 / 3))}^3 system (residual norm per sweep), "
+                      f"plain C FP64 oracle, {threads} OpenMP threads, {dt:.2f} s",
+            "sweeps_per_s": round(sweeps / dt, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_mib:
+        a = torch.empty(args.copy_mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_mib, "bytes_read_per_copy": a.numel() * 8,
+                          "bytes_written_per_copy": a.numel() * 8}), flush=True)
+        return
+    from paper_2112_02377_amd import binding as B
+    from paper_2112_02377_amd import workloads as W
+
+    N, K = args.N, args.sweeps
+    s = W.laplace7(N, workload=2)
+    stream = torch.cuda.Stream()
+    modes = {"JB": (B.JAC_BANDROW, 64, None), "JBO": (B.JAC_BANDROW_SP, 64, None),
+             "JSS": (B.JAC_SUBSTRUCT, 64, (8, 8, 8))}
+    sel = [m for m in args.modes.split(",") if m]
+    handles, infos, setup_s = {}, {}, {}
+    for m in sel:
+        mode, P, sub = modes[m]
+        t0 = time.perf_counter()
+        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=stream.cuda_stream)
+        B.jac_set_option(h, B.JAC_OPT_LOOP, args.loop)
+        if args.tile_rows:
+            B.jac_set_option(h, B.JAC_OPT_TILE_ROWS, args.tile_rows)
+        if args.block:
+            B.jac_set_option(h, B.JAC_OPT_BLOCK, args.block)
+        B.jac_set_grid(h, N, N, N)
+        B.jac_partition(h, mode, P, sub)
+        B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
+        torch.cuda.synchronize()
+        setup_s[m] = time.perf_counter() - t0
+        handles[m] = h
+        infos[m] = B.jac_get_info(h)
+    hist = torch.zeros(K, dtype=torch.float64, device="cuda")
+    loop_ms = {m: [] for m in sel}
+
+    def step(record):
+        for m in sel:
+            B.jac_set_x(handles[m], None)
+            B.jac_sweep(handles[m], K, hist)
+            if record:
+                loop_ms[m].append(B.jac_get_info(handles[m])["last_loop_ms"])
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step(True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    alg = {m: infos[m]["alg_bytes_per_sweep"] for m in sel}
+    total_bytes = args.steps * K * sum(alg.values())
+    value = total_bytes / (ms_total / 1e3) / 1e9
+    per_mode = {}
+    for m in sel:
+        avg = sum(loop_ms[m]) / len(loop_ms[m])
+        gbs = alg[m] * K / (avg / 1e3) / 1e9
+        i = infos[m]
+        per_mode[m] = {"loop_ms": round(avg, 3), "us_per_sweep": round(avg * 1e3 / K, 3),
+                       "sweeps_per_s": round(K / (avg / 1e3), 1), "GBps": round(gbs, 1),
+                       "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                       "dev_GBps": round(i["dev_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
+                       "col_bytes": i["col_bytes"], "halo_entries": i["halo_entries"],
+                       "staged_entries": i["staged_entries"], "ntiles": i["ntiles"], "grid": i["loop_grid"],
+                       "setup_s": round(setup_s[m], 2)}
+    # dominant kernel: the loop instantiation with the most time per step
+    kern = {}
+    for m in sel:
+        kname = "k_loop" if args.loop else "k_sweep"
+        tag = f"{kname}<double,1,staged>" if infos[m]["col_bytes"] == 2 else f"{kname}<double,1,global>"
+        kern.setdefault(tag, []).append(m)
+    dom = max(kern, key=lambda t: sum(per_mode[m]["loop_ms"] for m in kern[t]))
+    dm = kern[dom]
+    avg_launch_ms = sum(per_mode[m]["loop_ms"] for m in dm) / len(dm)
+    bytes_launch = sum(alg[m] for m in dm) / len(dm) * K
+    achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, bytes_launch),
+            "kernel": dom, "modes": dm, "alg_bytes_per_launch": int(bytes_launch),
+            "avg_launch_ms": round(avg_launch_ms, 3)}
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"laplace7 {N}^3 FP64, {K} sweeps x ({'+'.join(sel)}), 64 parts each "
+                                  f"(JSS: 8x8x8 subdomains)", "n": s.n, "nnz": s.nnz, "sweeps": K,
+                      "parallelism": "1 GPU", "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+           "roofline": roof, "modes": per_mode, "wall_s": round(wall, 3)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sweeps)
+    for h in handles.values():
+        B.jac_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,11 +78,15 @@ typedef enum {
     JAC_OPT_TILE_ROWS = 1,   /* max rows per tile (multiple of 64), default 1024    */
     JAC_OPT_BLOCK = 2,       /* threads per workgroup: 64..512, multiple of 64       */
     JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096   */
-    JAC_OPT_LOOP = 4,        /* 0 = persistent device loop, 1 = one launch per sweep */
+    JAC_OPT_LOOP = 4,        /* 0 = one launch per sweep (default), 1 = persistent
+                                cooperative loop with a grid barrier per sweep     */
     JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU (0 = occupancy)  */
     JAC_OPT_INNER_TOL = 6,   /* FP32 refinement: inner relative residual, x1e-9     */
     JAC_OPT_INNER_MAX = 7,   /* FP32 refinement: max inner sweeps per outer step    */
-    JAC_OPT_CKPT_MEM_MB = 8  /* adjoint: cap on segment buffers (MiB)               */
+    JAC_OPT_CKPT_MEM_MB = 8, /* adjoint: cap on segment buffers (MiB)               */
+    JAC_OPT_TIMING = 9       /* 1 = time each sweep loop with HIP events on the
+                                handle's stream (jac_info.last_loop_ms); the call
+                                then waits for the loop to finish                  */
 } jac_option;
 
 typedef struct {
@@ -94,10 +98,13 @@ typedef struct {
     int32_t col_bytes;           /* 4 = global int32 columns, 2 = tile-local u16    */
     int64_t halo_entries;        /* sum of the receive lists                        */
     int64_t staged_entries;      /* sum over tiles of staged x entries             */
-    int64_t alg_bytes_per_sweep; /* 12 nnz + 4 (n+1) + 32 n per right-hand side... */
+    int64_t alg_bytes_per_sweep; /* 12 nnz + 4 (n+1) + 8 n + 24 n nrhs (CSR model)   */
     int64_t dev_bytes_per_sweep; /* bytes the kernel actually streams per sweep     */
-    int32_t loop_grid;           /* workgroups of the persistent loop               */
+    int32_t loop_grid;           /* workgroups of the last sweep loop               */
     int32_t block;               /* threads per workgroup                           */
+    double last_loop_ms;         /* duration of the last sweep loop (JAC_OPT_TIMING) */
+    int32_t last_loop_sweeps;    /* sweeps that loop ran (incl. a final test sweep)  */
+    int32_t pad_;
 } jac_info;
 
 /* Create a system from host CSR arrays (row_ptr[n+1], col_idx[nnz],

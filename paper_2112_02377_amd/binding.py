@@ -24,7 +24,7 @@ JAC_BANDROW, JAC_BANDROW_SP, JAC_SUBSTRUCT = 1, 2, 3
 JAC_NORM_L2_REL, JAC_NORM_INF_ABS = 0, 1
 JAC_FP64, JAC_FP32_REFINE = 0, 1
 (JAC_OPT_TILE_ROWS, JAC_OPT_BLOCK, JAC_OPT_LDS_ELEMS, JAC_OPT_LOOP, JAC_OPT_WG_PER_CU, JAC_OPT_INNER_TOL,
- JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB) = range(1, 9)
+ JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING) = range(1, 10)
 
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
@@ -36,7 +36,8 @@ class jac_info(C.Structure):
                 ("nnz", C.c_int64), ("ell_slots", C.c_int64), ("ntiles", C.c_int32), ("nslices", C.c_int32),
                 ("max_footprint", C.c_int32), ("col_bytes", C.c_int32), ("halo_entries", C.c_int64),
                 ("staged_entries", C.c_int64), ("alg_bytes_per_sweep", C.c_int64),
-                ("dev_bytes_per_sweep", C.c_int64), ("loop_grid", C.c_int32), ("block", C.c_int32)]
+                ("dev_bytes_per_sweep", C.c_int64), ("loop_grid", C.c_int32), ("block", C.c_int32),
+                ("last_loop_ms", C.c_double), ("last_loop_sweeps", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -55,9 +55,10 @@ static jac_status guarded(F&& f)
 DevMem::~DevMem() { reset(); }
 void DevMem::reset()
 {
-    if (p) (void)hipFree(p);
+    if (p) (void)(pinned ? hipHostFree(p) : hipFree(p));
     p = nullptr;
     bytes = 0;
+    pinned = false;
 }
 void* DevMem::alloc(size_t nb)
 {
@@ -76,6 +77,13 @@ static void upload(DevMem& m, const std::vector<V>& v, hipStream_t st)
 }
 
 void Handle::sync() { JAC_HIP(hipStreamSynchronize(stream)); }
+
+Handle::~Handle()
+{
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (pev) (void)hipEventDestroy(pev);
+}
 
 // Rebuild the split and the sliced layout; keeps values, b and x.
 void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
@@ -130,7 +138,8 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     d.b.alloc((size_t)a.n * nrhs * sizeof(double));
     d.x0.alloc((size_t)a.n * nrhs * sizeof(double));
     d.x1.alloc((size_t)a.n * nrhs * sizeof(double));
-    d.tile_part.alloc((size_t)std::max(plan.ntiles, 1) * nrhs * sizeof(double));
+    d.x2.alloc((size_t)a.n * nrhs * sizeof(double));
+    d.tile_part.alloc(2 * (size_t)std::max(plan.ntiles, 1) * nrhs * sizeof(double));
     std::vector<int32_t> tb = {0, plan.ntiles};
     upload(d.tile_base, tb, stream);
     planned = true;
@@ -179,10 +188,16 @@ void Handle::update_bnorm()
     sync();
 }
 
+void Handle::settle(uint32_t which)
+{
+    launch_settle(static_cast<double*>(d.x0.p), static_cast<const double*>(d.x1.p), static_cast<const double*>(d.x2.p),
+                  a.n, nrhs, which, stream);
+}
+
 void Handle::get_x_dev(double* out)
 {
-    launch_scatter_out(static_cast<const double*>(d.x0.p), static_cast<const double*>(d.x1.p),
-                       static_cast<const int32_t*>(d.perm.p), a.n, nrhs, 0u, out, stream);
+    launch_scatter_out(static_cast<const double*>(d.x0.p), static_cast<const int32_t*>(d.perm.p), a.n, nrhs, out,
+                       stream);
 }
 
 SysDev Handle::sysdev(bool fp32) const
@@ -207,8 +222,9 @@ SysDev Handle::sysdev(bool fp32) const
         s.val = d.val.p;
         s.invd = d.invd.p;
         s.b = d.b.p;
-        s.x0 = d.x0.p;
-        s.x1 = d.x1.p;
+        s.x[0] = d.x0.p;
+        s.x[1] = d.x1.p;
+        s.x[2] = d.x2.p;
     }
     s.tile_part = static_cast<double*>(d.tile_part.p);
     s.n = a.n;
@@ -275,9 +291,15 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     p.kend = kend;
     p.solve = solve ? 1 : 0;
     p.norm_inf = norm_inf;
+    h.last_loop_sweeps = kend;
     const int64_t work = tile_base.back();
     const int block = h.opt.block;
-    if (h.opt.loop == 0 || nsys > 1) {
+    if (h.opt.timing) {
+        for (auto& e : h.ev)
+            if (!e) JAC_HIP(hipEventCreate(&e));
+        JAC_HIP(hipEventRecord(h.ev[0], st));
+    }
+    if (h.opt.loop == 1 || nsys > 1) {
         void* fn = sweep_kernel(fp32, nrhs, staged, true);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, nsys);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, work);
@@ -286,24 +308,49 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     } else {
         void* fn = sweep_kernel(fp32, nrhs, staged, false);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
-        const int grid = (int)std::max<int64_t>(1, work);
+        const int grid = (int)std::max<int64_t>(1, work) + 1;      // + the deciding workgroup
         h.last_grid = grid;
         if (!solve) {
             for (int32_t k = 0; k < kend; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);
+            launch_decide(nrhs, st, p, kend - 1);
         } else {
-            const int chunk = 32;
-            int32_t done = kRunning;
-            for (int32_t k = 0; k <= kend;) {
+            // Launch in chunks; while chunk j runs, look at the stop word copied
+            // after chunk j-1, so the device never waits for the host.
+            if (!h.d.poll.p) {
+                JAC_HIP(hipHostMalloc(&h.d.poll.p, 64, hipHostMallocDefault));
+                h.d.poll.bytes = 64;
+                h.d.poll.pinned = true;
+            }
+            volatile int32_t* poll = static_cast<int32_t*>(h.d.poll.p);
+            if (!h.pev) JAC_HIP(hipEventCreateWithFlags(&h.pev, hipEventDisableTiming));
+            const int chunk = 64;
+            int32_t k = 0;
+            int32_t seen_upto = -1;      // last launch whose stop word the pending copy holds
+            bool pending = false, stop = false;
+            while (!stop && k <= kend) {
                 const int32_t e = std::min<int32_t>(kend + 1, k + chunk);
                 for (; k < e; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);
-                JAC_HIP(hipMemcpyAsync(&done, &static_cast<SysState*>(d_state.p)[0].done_k, sizeof(int32_t),
+                if (pending) {
+                    JAC_HIP(hipEventSynchronize(h.pev));
+                    if (poll[0] <= seen_upto) stop = true;
+                }
+                JAC_HIP(hipMemcpyAsync(h.d.poll.p, &static_cast<SysState*>(d_state.p)[0].done_k, sizeof(int32_t),
                                        hipMemcpyDeviceToHost, st));
-                h.sync();
-                if (done <= k) break;
+                JAC_HIP(hipEventRecord(h.pev, st));
+                pending = true;
+                seen_upto = k - 1;
             }
+            if (!stop) launch_decide(nrhs, st, p, kend);
         }
     }
     JAC_HIP(hipGetLastError());
+    if (h.opt.timing) {
+        JAC_HIP(hipEventRecord(h.ev[1], st));
+        JAC_HIP(hipEventSynchronize(h.ev[1]));
+        float ms = 0.f;
+        JAC_HIP(hipEventElapsedTime(&ms, h.ev[0], h.ev[1]));
+        h.last_loop_ms = ms;
+    }
 }
 
 }  // namespace jac
@@ -477,8 +524,9 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double* hist_dev)
         std::vector<int32_t> tb = {0, h->plan.ntiles};
         run_loop(*h, sys, false, false, nsweeps, 0, hist_dev, h->d.sys, h->d.state, h->d.tile_base, tb,
                  h->lds_fp_bytes(false), h->lds_runs(), h->plan.prm.staged, h->nrhs);
-        launch_settle(static_cast<double*>(h->d.x0.p), static_cast<const double*>(h->d.x1.p), h->a.n, h->nrhs,
-                      (nsweeps & 1) ? 0xFu : 0u, h->stream);
+        uint32_t which = 0;
+        for (int c = 0; c < h->nrhs; ++c) which |= (uint32_t)(nsweeps % 3) << (2 * c);
+        h->settle(which);
         return JAC_OK;
     });
 }
@@ -501,14 +549,14 @@ static jac_status solve64(Handle& h, double tol, int32_t maxit, int norm, int32_
     SysState st;
     JAC_HIP(hipMemcpyAsync(&st, h.d.state.p, sizeof(SysState), hipMemcpyDeviceToHost, h.stream));
     h.sync();
-    uint32_t use_x1 = 0;
+    uint32_t which = 0;
+    h.last_loop_sweeps = st.last_k + 1;
     for (int c = 0; c < h.nrhs; ++c) {
-        if (st.stop_k[c] & 1) use_x1 |= 1u << c;
+        which |= (uint32_t)(st.stop_k[c] % 3) << (2 * c);
         if (sweeps_out) sweeps_out[c] = st.stop_k[c];
         if (relres_out) relres_out[c] = st.nrm[c] / scale[c];
     }
-    launch_settle(static_cast<double*>(h.d.x0.p), static_cast<const double*>(h.d.x1.p), h.a.n, h.nrhs, use_x1,
-                  h.stream);
+    h.settle(which);
     h.last_status = st.status;
     if (st.status == JAC_E_DIVERGED) fail(JAC_E_DIVERGED, "residual norm diverged");
     return (jac_status)st.status;
@@ -570,14 +618,13 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         jac_status worst = JAC_OK;
         for (int32_t s = 0; s < nsys; ++s) {
             Handle& h = *hs[s];
-            uint32_t use_x1 = 0;
+            uint32_t which = 0;
             for (int c = 0; c < h.nrhs; ++c) {
-                if (st[s].stop_k[c] & 1) use_x1 |= 1u << c;
+                which |= (uint32_t)(st[s].stop_k[c] % 3) << (2 * c);
                 if (sweeps_out) sweeps_out[(size_t)s * 4 + c] = st[s].stop_k[c];
                 if (relres_out) relres_out[(size_t)s * 4 + c] = st[s].nrm[c] / scale[(size_t)s * 4 + c];
             }
-            launch_settle(static_cast<double*>(h.d.x0.p), static_cast<const double*>(h.d.x1.p), h.a.n, h.nrhs,
-                          use_x1, h0.stream);
+            h.settle(which);
             if (st[s].status == JAC_E_DIVERGED) worst = JAC_E_DIVERGED;
             else if (st[s].status == JAC_NOT_CONVERGED && worst == JAC_OK) worst = JAC_NOT_CONVERGED;
         }
@@ -617,6 +664,9 @@ jac_status jac_set_option(jac_handle h, jac_option opt, int64_t v)
         case JAC_OPT_CKPT_MEM_MB:
             if (v < 1) fail(JAC_E_INVALID, "checkpoint memory >= 1 MiB");
             o.ckpt_mb = v; break;
+        case JAC_OPT_TIMING:
+            if (v != 0 && v != 1) fail(JAC_E_INVALID, "timing: 0 or 1");
+            o.timing = (int32_t)v; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -637,6 +687,7 @@ jac_status jac_get_option(jac_handle h, jac_option opt, int64_t* v)
         case JAC_OPT_INNER_TOL: *v = (int64_t)std::llround(o.inner_tol * 1e9); break;
         case JAC_OPT_INNER_MAX: *v = o.inner_max; break;
         case JAC_OPT_CKPT_MEM_MB: *v = o.ckpt_mb; break;
+        case JAC_OPT_TIMING: *v = o.timing; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -668,6 +719,8 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.dev_bytes_per_sweep = dev;
         i.loop_grid = h->last_grid;
         i.block = h->opt.block;
+        i.last_loop_ms = h->last_loop_ms;
+        i.last_loop_sweeps = h->last_loop_sweeps;
         *info = i;
         return JAC_OK;
     });

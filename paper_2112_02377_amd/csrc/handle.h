@@ -16,6 +16,7 @@ namespace jac {
 struct DevMem {
     void* p = nullptr;
     size_t bytes = 0;
+    bool pinned = false;       // host pinned memory (hipHostMalloc)
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
@@ -28,11 +29,12 @@ struct Options {
     int32_t tile_rows = 1024;
     int32_t block = 256;
     int32_t lds_elems = 4096;
-    int32_t loop = 0;          // 0 persistent, 1 launch per sweep
+    int32_t loop = 0;          // 0 one launch per sweep, 1 persistent cooperative loop
     int32_t wg_per_cu = 0;
     double inner_tol = 1e-5;
     int32_t inner_max = 256;
     int64_t ckpt_mb = 4096;
+    int32_t timing = 0;
 };
 
 struct DeviceArrays {
@@ -41,7 +43,8 @@ struct DeviceArrays {
     DevMem slot_of_caller, diag_slot, perm;
     DevMem vals_caller, b_caller;          // caller order, kept for re-planning
     DevMem val, val32, invd, invd32;
-    DevMem b, x0, x1, tile_part, tile_base;
+    DevMem b, x0, x1, x2, tile_part, tile_base;
+    DevMem poll;                           // pinned host word for stop polling
     DevMem sys, state, bar, bad, norm_part, bnorm;
     DevMem batch_sys, batch_state, batch_tile_base;
     // FP32 refinement
@@ -65,6 +68,11 @@ struct Handle {
     double bnorm[4] = {0, 0, 0, 0};
     int last_grid = 0;
     int last_status = 0;
+    double last_loop_ms = 0.0;
+    int32_t last_loop_sweeps = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t pev = nullptr;
+    ~Handle();
     // adjoint: plan of A^T (built on first use)
     bool have_t = false;
     Plan tplan;
@@ -76,6 +84,7 @@ struct Handle {
     void ensure_fp32();
     void update_bnorm();
     void get_x_dev(double* out);
+    void settle(uint32_t which);
     SysDev sysdev(bool fp32) const;
     int lds_fp_bytes(bool fp32) const;
     int lds_runs() const;

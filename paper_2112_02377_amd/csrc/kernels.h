@@ -27,9 +27,8 @@ struct SysDev {
     const void* val;          // slot values, T
     const void* invd;         // D^{-1}, T
     const void* b;            // right-hand sides, T, node-major [n][nrhs]
-    void* x0;                 // iterate buffers, T, node-major [n][nrhs]
-    void* x1;
-    double* tile_part;        // [ntiles][nrhs] per-tile norm partials
+    void* x[3];               // iterate buffers, T, node-major [n][nrhs]; x_k lives in x[k % 3]
+    double* tile_part;        // [2][ntiles][nrhs] per-tile norm partials, by sweep parity
     int32_t n, ntiles, nrhs, staged;
     double thr[4];            // stop thresholds per right-hand side
     double big[4];            // divergence thresholds per right-hand side
@@ -47,6 +46,12 @@ struct SysState {
     double nrm[4];            // norms of the last reduced residual
 };
 
+// Sweep control.  One launch per sweep: the stop decision on the residual of
+// sweep k is taken by a dedicated workgroup of launch k+1 (or by the closing
+// reduction launch), so launches never synchronise inside a kernel; a third
+// iterate buffer keeps x_k intact while launch k+1 computes x_{k+2}
+// speculatively.  Persistent loop: the decision is taken by the workgroup that
+// finishes the last tile of a system, before the sweep's grid barrier.
 struct LoopParams {
     const SysDev* sys;        // [nsys]
     SysState* st;             // [nsys]

@@ -33,9 +33,41 @@ namespace {
 constexpr int KB = 8;      // slot batch: loads issued together before use
 constexpr int SU = 4;      // staging batch
 
-__device__ __forceinline__ int32_t ld_acquire(const int32_t* p)
+// Pointer into global (device) memory: lets the compiler emit global_* loads.
+template <typename V>
+using gptr = __attribute__((address_space(1))) V*;
+
+// Coherent (device-wide) relaxed accesses for the few words workgroups of one
+// persistent launch exchange; no cache-wide maintenance is implied.
+__device__ __forceinline__ int32_t ld_dev(const int32_t* p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int32_t* p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Plain or coherent access, chosen at compile time.
+template <bool DEV, typename V>
+__device__ __forceinline__ V ldv(const V* p)
+{
+    if constexpr (DEV) return ld_dev(p);
+    else return *p;
+}
+template <bool DEV, typename V>
+__device__ __forceinline__ void stv(V* p, V v)
+{
+    if constexpr (DEV) st_dev(p, v);
+    else *p = v;
 }
 
 __device__ __forceinline__ double maxnan(double a, double b)
@@ -79,10 +111,12 @@ __device__ __forceinline__ void block_reduce(double (&v)[NRHS], bool is_max, dou
     __syncthreads();
 }
 
-// Tile of WG-independent work: XCD-aware order.  Workgroup ids are dealt to
-// the 8 XCDs round-robin; item ranges are given to XCDs as contiguous blocks
-// (floor rule) so that neighbouring tiles, which share x halos, meet in the
-// same L2.  Returns the first item of this workgroup and its stride.
+// Items [0,T) shared by G workgroups, XCD-aware.  Workgroup ids are dealt to
+// the 8 XCDs round-robin, so XCD x holds workgroups x, x+8, ...; each XCD gets
+// one contiguous block of items (sizes differing by at most one, the same
+// split as its workgroup count when G == T, so then every workgroup gets
+// exactly one item) and neighbouring tiles, which share x halos, meet in the
+// same L2.
 __device__ __forceinline__ void xcd_items(int32_t T, int32_t G, int32_t wg, int32_t& first, int32_t& end,
                                           int32_t& stride)
 {
@@ -92,35 +126,43 @@ __device__ __forceinline__ void xcd_items(int32_t T, int32_t G, int32_t wg, int3
     }
     const int32_t x = wg & 7, l = wg >> 3;
     const int32_t gx = (G - x + 7) >> 3;                  // workgroups on this XCD
-    const int64_t s0 = ((int64_t)x * T) >> 3, s1 = ((int64_t)(x + 1) * T) >> 3;
-    first = (int32_t)s0 + l;
-    end = (int32_t)s1;
+    const int32_t q = T >> 3, r = T & 7;
+    const int32_t s0 = x * q + min(x, r);
+    first = s0 + l;
+    end = s0 + q + (x < r ? 1 : 0);
     stride = gx;
 }
 
 // ---------------------------------------------------------------------------
-// One tile of one sweep.
+// One tile of one sweep: stage the footprint (staged tiles), then one slice
+// of 64 rows per wavefront; accumulates the tile's residual norm partial.
 // ---------------------------------------------------------------------------
 template <typename T, int NRHS, bool STAGED>
-__device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, int32_t k, uint32_t frozen, bool is_max,
-                                           T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
+__device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
+                                           bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
                                            int32_t* __restrict__ lds_ro, double (&acc)[NRHS])
 {
-    const T* __restrict__ x = reinterpret_cast<const T*>((k & 1) ? S.x1 : S.x0);
-    T* __restrict__ xn = reinterpret_cast<T*>((k & 1) ? S.x0 : S.x1);
-    const T* __restrict__ val = reinterpret_cast<const T*>(S.val);
-    const T* __restrict__ invd = reinterpret_cast<const T*>(S.invd);
-    const T* __restrict__ b = reinterpret_cast<const T*>(S.b);
-    const int32_t r0 = S.tile_row0[tile], r1 = S.tile_row0[tile + 1];
+    // every array below is device memory: global address space for the loads
+    const gptr<const T> x = (gptr<const T>)x_;
+    const gptr<T> xn = (gptr<T>)xn_;
+    const gptr<const T> val = (gptr<const T>)S.val;
+    const gptr<const T> invd = (gptr<const T>)S.invd;
+    const gptr<const T> b = (gptr<const T>)S.b;
+    const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
+    const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
+    const int32_t r0 = __builtin_amdgcn_readfirstlane(S.tile_row0[tile]);
+    const int32_t r1 = __builtin_amdgcn_readfirstlane(S.tile_row0[tile + 1]);
     int32_t own = 0;
     if constexpr (STAGED) {
-        const int32_t run0 = S.tile_run0[tile];
-        const int32_t nr = S.tile_run0[tile + 1] - run0;
-        const int32_t fp = S.tile_fp[tile];
-        own = S.tile_own[tile];
+        const gptr<const int32_t> run_start = (gptr<const int32_t>)S.run_start;
+        const gptr<const int32_t> run_lds = (gptr<const int32_t>)S.run_lds;
+        const int32_t run0 = __builtin_amdgcn_readfirstlane(S.tile_run0[tile]);
+        const int32_t nr = __builtin_amdgcn_readfirstlane(S.tile_run0[tile + 1]) - run0;
+        const int32_t fp = __builtin_amdgcn_readfirstlane(S.tile_fp[tile]);
+        own = __builtin_amdgcn_readfirstlane(S.tile_own[tile]);
         for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) {
-            lds_rs[t] = S.run_start[run0 + t];
-            lds_ro[t] = S.run_lds[run0 + t];
+            lds_rs[t] = run_start[run0 + t];
+            lds_ro[t] = run_lds[run0 + t];
         }
         __syncthreads();
         for (int32_t e0 = threadIdx.x; e0 < fp; e0 += blockDim.x * SU) {
@@ -155,12 +197,18 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, int32_
         }
         __syncthreads();
     }
-    const int32_t s0 = S.tile_slice0[tile], s1 = S.tile_slice0[tile + 1];
-    const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int32_t s0 = __builtin_amdgcn_readfirstlane(S.tile_slice0[tile]);
+    const int32_t s1 = __builtin_amdgcn_readfirstlane(S.tile_slice0[tile + 1]);
+    // wave-uniform values kept in scalar registers
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    const int32_t lane = threadIdx.x & 63;
     for (int32_t s = s0 + wave; s < s1; s += nw) {
-        const int32_t row0 = S.slice_row0[s];
-        const int32_t w = S.slice_width[s];
-        const int64_t off = S.slice_off[s] + lane;
+        const int32_t row0 = __builtin_amdgcn_readfirstlane(S.slice_row0[s]);
+        const int32_t w = __builtin_amdgcn_readfirstlane(S.slice_width[s]);
+        const int64_t soff = S.slice_off[s];
+        const int64_t off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(soff >> 32)) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)soff)) + lane;
         const int32_t i = row0 + lane;
         T q[NRHS];
 #pragma unroll
@@ -172,9 +220,9 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, int32_
             for (int u = 0; u < KB; ++u)
                 if (k0 + u < w) {
                     const int64_t slot = off + (int64_t)(k0 + u) * 64;
-                    a[u] = val[slot];
-                    if constexpr (STAGED) col[u] = S.col16[slot];
-                    else col[u] = S.col32[slot];
+                    a[u] = __builtin_nontemporal_load(&val[slot]);
+                    if constexpr (STAGED) col[u] = __builtin_nontemporal_load(&col16[slot]);
+                    else col[u] = __builtin_nontemporal_load(&col32[slot]);
                 }
             T xv[KB][NRHS];
 #pragma unroll
@@ -210,90 +258,107 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, int32_
     if constexpr (STAGED) __syncthreads();   // LDS is reused by the next tile
 }
 
-// Sum (or max) the tile partials of system s in tile order, then take the
-// stop decision for sweep k.  Runs in the workgroup that finished the last
-// tile of s in this sweep.
-template <int NRHS>
-__device__ void reduce_and_decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& S, double* red)
+// Reduce the tile partials of sweep k of system s in tile order and take the
+// stop decision on r_k.  DEV selects coherent accesses (persistent launch,
+// where other workgroups of the same launch wrote the partials) or plain ones
+// (a later launch: the kernel boundary made them visible).
+template <int NRHS, bool DEV>
+__device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& S, double* red)
 {
+    SysState* st = &P.st[s];
+    if (ldv<DEV>(&st->done_k) <= k) return;                 // already decided (launches past the stop)
     double v[NRHS];
 #pragma unroll
     for (int c = 0; c < NRHS; ++c) v[c] = 0.0;
     const bool is_max = P.norm_inf != 0;
+    const double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
     for (int32_t t = threadIdx.x; t < S.ntiles; t += blockDim.x) {
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) {
-            const double p = __builtin_nontemporal_load(&S.tile_part[(int64_t)t * NRHS + c]);
+            const double p = ldv<DEV>(&part[(int64_t)t * NRHS + c]);
             v[c] = is_max ? maxnan(v[c], p) : v[c] + p;
         }
     }
     block_reduce<NRHS>(v, is_max, red);
     if (threadIdx.x == 0) {
-        SysState* st = &P.st[s];
         bool running = false, diverged = false, exhausted = false;
         for (int c = 0; c < S.nrhs; ++c) {
-            if (st->stop_k[c] < k) continue;             // frozen earlier
+            if (ldv<DEV>(&st->stop_k[c]) < k) continue;   // frozen earlier
             const double nrm = is_max ? v[c] : sqrt(v[c]);
-            st->nrm[c] = nrm;
+            stv<DEV>(&st->nrm[c], nrm);
             if (P.hist && s == 0) P.hist[(int64_t)(k - P.k0) * S.nrhs + c] = nrm;
             if (!P.solve) { running = true; continue; }
             if (!(nrm <= S.big[c])) { diverged = true; continue; }
-            if (nrm <= S.thr[c]) { st->stop_k[c] = k; continue; }
-            if (k >= P.kend) { st->stop_k[c] = k; exhausted = true; continue; }
+            if (nrm <= S.thr[c]) { stv<DEV>(&st->stop_k[c], k); continue; }
+            if (k >= P.kend) { stv<DEV>(&st->stop_k[c], k); exhausted = true; continue; }
             running = true;
         }
         if (diverged) {
             for (int c = 0; c < S.nrhs; ++c)
-                if (st->stop_k[c] >= k) st->stop_k[c] = k;
-            st->status = JAC_E_DIVERGED;
+                if (ldv<DEV>(&st->stop_k[c]) >= k) stv<DEV>(&st->stop_k[c], k);
+            stv<DEV>(&st->status, (int32_t)JAC_E_DIVERGED);
             running = false;
-        } else if (exhausted && st->status == JAC_OK) {
-            st->status = JAC_NOT_CONVERGED;
+        } else if (exhausted && ldv<DEV>(&st->status) == JAC_OK) {
+            stv<DEV>(&st->status, (int32_t)JAC_NOT_CONVERGED);
         }
-        st->last_k = k;
-        if (!running && P.solve) st->done_k = k + 1;
-        __hip_atomic_store(&st->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        stv<DEV>(&st->last_k, k);
+        if (!running && P.solve) stv<DEV>(&st->done_k, k + 1);
     }
 }
 
-// One tile of sweep k plus its partial, arrival and (if last) the decision.
+// ---------------------------------------------------------------------------
+// One launch per sweep (single system).  Workgroups 0..ntiles-1 sweep one tile
+// each; the last workgroup takes the stop decision on the previous sweep.
+// ---------------------------------------------------------------------------
 template <typename T, int NRHS, bool STAGED>
-__device__ __forceinline__ void tile_step(const LoopParams& P, int32_t s, int32_t tile, int32_t k, char* smem,
-                                          int32_t lds_fp_bytes, int32_t lds_runs)
+__global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
 {
-    const SysDev& S = P.sys[s];
+    extern __shared__ __align__(16) char smem[];
+    const SysDev& S = P.sys[0];
     T* lds_x = reinterpret_cast<T*>(smem);
     int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
     int32_t* lds_ro = lds_rs + lds_runs;
     double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
-    int32_t* flag = reinterpret_cast<int32_t*>(red + 16 * 4);
-    uint32_t frozen = 0;
-    for (int c = 0; c < NRHS; ++c)
-        if (ld_acquire(&P.st[s].stop_k[c]) < k) frozen |= 1u << c;
-    const bool is_max = P.norm_inf != 0;
-    double acc[NRHS];
-#pragma unroll
-    for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-    sweep_tile<T, NRHS, STAGED>(S, tile, k, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
-    block_reduce<NRHS>(acc, is_max, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < NRHS; ++c) S.tile_part[(int64_t)tile * NRHS + c] = acc[c];
-        __threadfence();
-        const uint32_t old =
-            __hip_atomic_fetch_add(&P.st[s].arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *flag = (old == (uint32_t)S.ntiles - 1u) ? 1 : 0;
+    if (blockIdx.x == gridDim.x - 1) {
+        if (k > P.k0) decide<NRHS, false>(P, 0, k - 1, S, red);
+        return;
     }
-    __syncthreads();
-    const bool last = *flag != 0;
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        reduce_and_decide<NRHS>(P, s, k, S, red);
+    const SysState* st = P.st;
+    if (st->done_k <= k) return;
+    uint32_t frozen = 0;
+#pragma unroll
+    for (int c = 0; c < NRHS; ++c)
+        if (st->stop_k[c] < k) frozen |= 1u << c;
+    int32_t first, end, stride;
+    xcd_items(S.ntiles, gridDim.x - 1, blockIdx.x, first, end, stride);
+    const bool is_max = P.norm_inf != 0;
+    const T* x = reinterpret_cast<const T*>(S.x[k % 3]);
+    T* xn = reinterpret_cast<T*>(S.x[(k + 1) % 3]);
+    double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
+    for (int32_t tile = first; tile < end; tile += stride) {
+        double acc[NRHS];
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
+        sweep_tile<T, NRHS, STAGED>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        block_reduce<NRHS>(acc, is_max, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) part[(int64_t)tile * NRHS + c] = acc[c];
+        }
     }
 }
 
+// Closing reduction: the stop decision on the last swept residual.
+template <int NRHS>
+__global__ void __launch_bounds__(512) k_decide(LoopParams P, int32_t k)
+{
+    __shared__ double red[16 * 4];
+    decide<NRHS, false>(P, 0, k, P.sys[0], red);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent loop: every sweep of every system in one cooperative launch.
+// ---------------------------------------------------------------------------
 __device__ void grid_barrier(uint32_t* bar, uint32_t G)
 {
     __syncthreads();
@@ -301,16 +366,18 @@ __device__ void grid_barrier(uint32_t* bar, uint32_t G)
         uint32_t* count = bar;
         uint32_t* gen = bar + 1;
         const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // release this workgroup's iterate writes device-wide
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == G - 1) {
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0)
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0)
                 __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        // acquire the other workgroups' writes
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -325,7 +392,7 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
     for (int32_t base = 0; base < P.nsys; base += blockDim.x) {
         const int32_t s = base + threadIdx.x;
         int32_t cnt = 0;
-        if (s < P.nsys && ld_acquire(&P.st[s].done_k) > k) cnt = P.tile_base[s + 1] - P.tile_base[s];
+        if (s < P.nsys && ld_dev(&P.st[s].done_k) > k) cnt = P.tile_base[s + 1] - P.tile_base[s];
         int32_t inc = cnt;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -346,17 +413,19 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
     return carry;
 }
 
-// ---------------------------------------------------------------------------
-// Persistent loop: all sweeps of all systems in one cooperative launch, one
-// grid barrier per sweep.
-// ---------------------------------------------------------------------------
 template <typename T, int NRHS, bool STAGED>
 __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
-    int32_t* pref = reinterpret_cast<int32_t*>(smem + lds_fp_bytes + 2 * lds_runs * 4 + 16 * 4 * 8 + 16);
+    T* lds_x = reinterpret_cast<T*>(smem);
+    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    int32_t* lds_ro = lds_rs + lds_runs;
+    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t* flag = reinterpret_cast<int32_t*>(red + 16 * 4);
+    int32_t* pref = flag + 4;
     int32_t* wsum = pref + P.nsys + 1;
     const int32_t G = gridDim.x;
+    const bool is_max = P.norm_inf != 0;
     for (int32_t k = P.k0;; ++k) {
         if (!P.solve && k >= P.kend) break;
         const int32_t T_act = build_work(P, k, pref, wsum);
@@ -369,22 +438,40 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
                 const int32_t mid = (lo + hi + 1) >> 1;
                 if (pref[mid] <= j) lo = mid; else hi = mid - 1;
             }
-            tile_step<T, NRHS, STAGED>(P, lo, j - pref[lo], k, smem, lds_fp_bytes, lds_runs);
+            const int32_t sidx = lo, tile = j - pref[lo];
+            const SysDev& S = P.sys[sidx];
+            SysState* sst = &P.st[sidx];
+            uint32_t frozen = 0;
+            for (int c = 0; c < NRHS; ++c)
+                if (ld_dev(&sst->stop_k[c]) < k) frozen |= 1u << c;
+            double acc[NRHS];
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
+            sweep_tile<T, NRHS, STAGED>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
+                                        reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs,
+                                        lds_ro, acc);
+            block_reduce<NRHS>(acc, is_max, red);
+            if (threadIdx.x == 0) {
+                double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
+#pragma unroll
+                for (int c = 0; c < NRHS; ++c) st_dev(&part[(int64_t)tile * NRHS + c], acc[c]);
+                // the partial is complete device-wide before the arrival counts it
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                const uint32_t old =
+                    __hip_atomic_fetch_add(&sst->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *flag = (old == (uint32_t)S.ntiles - 1u) ? 1 : 0;
+            }
+            __syncthreads();
+            const bool last = *flag != 0;
+            __syncthreads();
+            if (last) {
+                decide<NRHS, true>(P, sidx, k, S, red);
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&sst->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         grid_barrier(P.bar, (uint32_t)G);
     }
-}
-
-// One launch per sweep (single system): same tile work, stream order as the
-// barrier.  Sweeps after the stop decision return at once.
-template <typename T, int NRHS, bool STAGED>
-__global__ void __launch_bounds__(512) k_sweep1(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
-{
-    extern __shared__ __align__(16) char smem[];
-    if (ld_acquire(&P.st[0].done_k) <= k) return;
-    int32_t first, end, stride;
-    xcd_items(P.sys[0].ntiles, gridDim.x, blockIdx.x, first, end, stride);
-    for (int32_t j = first; j < end; j += stride) tile_step<T, NRHS, STAGED>(P, 0, j, k, smem, lds_fp_bytes, lds_runs);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,27 +513,27 @@ __global__ void k_gather_in(const double* __restrict__ src, const int32_t* __res
     }
 }
 
-// internal [new row][c] of the buffer holding each column's result -> caller [c][n]
-__global__ void k_scatter_out(const double* __restrict__ x0, const double* __restrict__ x1,
-                              const int32_t* __restrict__ perm, int32_t n, int32_t nrhs, uint32_t use_x1,
-                              double* __restrict__ dst)
+// internal [new row][c] -> caller [c][n] (original order)
+__global__ void k_scatter_out(const double* __restrict__ x, const int32_t* __restrict__ perm, int32_t n,
+                              int32_t nrhs, double* __restrict__ dst)
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int32_t o = perm[i];
-        for (int c = 0; c < nrhs; ++c) {
-            const double* x = ((use_x1 >> c) & 1u) ? x1 : x0;
-            dst[(int64_t)c * n + o] = x[(int64_t)i * nrhs + c];
-        }
+        for (int c = 0; c < nrhs; ++c) dst[(int64_t)c * n + o] = x[(int64_t)i * nrhs + c];
     }
 }
 
-// Move columns whose result sits in buffer 1 back to buffer 0.
-__global__ void k_settle(double* __restrict__ x0, const double* __restrict__ x1, int32_t n, int32_t nrhs,
-                         uint32_t use_x1)
+// Move every column's result to buffer 0; which[c] (2 bits per column) names
+// the buffer holding it.
+__global__ void k_settle(double* __restrict__ x0, const double* __restrict__ x1, const double* __restrict__ x2,
+                         int32_t n, int32_t nrhs, uint32_t which)
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        for (int c = 0; c < nrhs; ++c)
-            if ((use_x1 >> c) & 1u) x0[(int64_t)i * nrhs + c] = x1[(int64_t)i * nrhs + c];
+        for (int c = 0; c < nrhs; ++c) {
+            const uint32_t w = (which >> (2 * c)) & 3u;
+            if (w == 1u) x0[(int64_t)i * nrhs + c] = x1[(int64_t)i * nrhs + c];
+            else if (w == 2u) x0[(int64_t)i * nrhs + c] = x2[(int64_t)i * nrhs + c];
+        }
 }
 
 __global__ void k_init_state(SysState* st, int32_t nsys, int32_t nrhs_unused)
@@ -501,20 +588,21 @@ __global__ void k_colnorm_final(const double* __restrict__ part, int32_t nblocks
 namespace {
 
 template <typename T, int NRHS, bool STAGED>
-void* loop_fn() { return reinterpret_cast<void*>(&k_loop<T, NRHS, STAGED>); }
-template <typename T, int NRHS, bool STAGED>
-void* sweep1_fn() { return reinterpret_cast<void*>(&k_sweep1<T, NRHS, STAGED>); }
+void* kfn(bool loop)
+{
+    return loop ? reinterpret_cast<void*>(&k_loop<T, NRHS, STAGED>) : reinterpret_cast<void*>(&k_sweep<T, NRHS, STAGED>);
+}
 
 template <typename T>
 void* pick(int nrhs, bool staged, bool loop)
 {
     switch (nrhs * 2 + (staged ? 1 : 0)) {
-    case 2: return loop ? loop_fn<T, 1, false>() : sweep1_fn<T, 1, false>();
-    case 3: return loop ? loop_fn<T, 1, true>() : sweep1_fn<T, 1, true>();
-    case 4: return loop ? loop_fn<T, 2, false>() : sweep1_fn<T, 2, false>();
-    case 5: return loop ? loop_fn<T, 2, true>() : sweep1_fn<T, 2, true>();
-    case 8: return loop ? loop_fn<T, 4, false>() : sweep1_fn<T, 4, false>();
-    case 9: return loop ? loop_fn<T, 4, true>() : sweep1_fn<T, 4, true>();
+    case 2: return kfn<T, 1, false>(loop);
+    case 3: return kfn<T, 1, true>(loop);
+    case 4: return kfn<T, 2, false>(loop);
+    case 5: return kfn<T, 2, true>(loop);
+    case 8: return kfn<T, 4, false>(loop);
+    case 9: return kfn<T, 4, true>(loop);
     default: return nullptr;
     }
 }
@@ -556,6 +644,16 @@ void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, Lo
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 
+void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k)
+{
+    switch (nrhs) {
+    case 1: k_decide<1><<<1, 256, 0, st>>>(p, k); break;
+    case 2: k_decide<2><<<1, 256, 0, st>>>(p, k); break;
+    default: k_decide<4><<<1, 256, 0, st>>>(p, k); break;
+    }
+    JAC_HIP(hipGetLastError());
+}
+
 void launch_scatter_vals(const double* vals, const int32_t* slot_of, int64_t nnz, double* out, hipStream_t st)
 {
     if (nnz > 0) k_scatter_vals<<<grid1d(nnz), 256, 0, st>>>(vals, slot_of, nnz, out);
@@ -581,16 +679,16 @@ void launch_gather_in(const double* src, const int32_t* perm, int32_t n, int32_t
     JAC_HIP(hipGetLastError());
 }
 
-void launch_scatter_out(const double* x0, const double* x1, const int32_t* perm, int32_t n, int32_t nrhs,
-                        uint32_t use_x1, double* dst, hipStream_t st)
+void launch_scatter_out(const double* x, const int32_t* perm, int32_t n, int32_t nrhs, double* dst, hipStream_t st)
 {
-    if (n > 0) k_scatter_out<<<grid1d(n), 256, 0, st>>>(x0, x1, perm, n, nrhs, use_x1, dst);
+    if (n > 0) k_scatter_out<<<grid1d(n), 256, 0, st>>>(x, perm, n, nrhs, dst);
     JAC_HIP(hipGetLastError());
 }
 
-void launch_settle(double* x0, const double* x1, int32_t n, int32_t nrhs, uint32_t use_x1, hipStream_t st)
+void launch_settle(double* x0, const double* x1, const double* x2, int32_t n, int32_t nrhs, uint32_t which,
+                   hipStream_t st)
 {
-    if (n > 0 && use_x1) k_settle<<<grid1d(n), 256, 0, st>>>(x0, x1, n, nrhs, use_x1);
+    if (n > 0 && which) k_settle<<<grid1d(n), 256, 0, st>>>(x0, x1, x2, n, nrhs, which);
     JAC_HIP(hipGetLastError());
 }
 

@@ -18,15 +18,16 @@ void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, Loop
                  int lds_runs, bool cooperative);
 void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
                    int lds_fp_bytes, int lds_runs);
+void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k);
 
 void launch_scatter_vals(const double* vals, const int32_t* slot_of, int64_t nnz, double* out, hipStream_t st);
 void launch_invd(const double* val, const int32_t* diag_slot, int32_t n, double* invd, float* invd32, int32_t* bad,
                  hipStream_t st);
 void launch_to_f32(const double* in, int64_t m, float* out, hipStream_t st);
 void launch_gather_in(const double* src, const int32_t* perm, int32_t n, int32_t nrhs, double* dst, hipStream_t st);
-void launch_scatter_out(const double* x0, const double* x1, const int32_t* perm, int32_t n, int32_t nrhs,
-                        uint32_t use_x1, double* dst, hipStream_t st);
-void launch_settle(double* x0, const double* x1, int32_t n, int32_t nrhs, uint32_t use_x1, hipStream_t st);
+void launch_scatter_out(const double* x, const int32_t* perm, int32_t n, int32_t nrhs, double* dst, hipStream_t st);
+void launch_settle(double* x0, const double* x1, const double* x2, int32_t n, int32_t nrhs, uint32_t which,
+                   hipStream_t st);
 void launch_init_state(SysState* s, int32_t nsys, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int32_t m, hipStream_t st);
 void launch_colnorm(const double* b, int32_t n, int32_t nrhs, double* part, double* out, hipStream_t st);
