@@ -75,7 +75,7 @@ typedef enum {
 
 /* Tunables (jac_set_option / jac_get_option). */
 typedef enum {
-    JAC_OPT_TILE_ROWS = 1,   /* max rows per tile (multiple of 64), default 1024    */
+    JAC_OPT_TILE_ROWS = 1,   /* max rows per tile (multiple of 64), default 512     */
     JAC_OPT_BLOCK = 2,       /* threads per workgroup: 64..512, multiple of 64       */
     JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096   */
     JAC_OPT_LOOP = 4,        /* 0 = one launch per sweep (default), 1 = persistent

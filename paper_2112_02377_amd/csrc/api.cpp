@@ -114,7 +114,11 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     upload(d.slice_row0, plan.slice_row0, stream);
     upload(d.slice_width, plan.slice_width, stream);
     upload(d.slice_off, plan.slice_off, stream);
-    if (plan.prm.staged) {
+    if (plan.colfmt == COL_REL16) {
+        upload(d.col16, plan.col16, stream);
+        d.col32.reset();
+        d.tile_run0.reset(); d.run_start.reset(); d.run_lds.reset(); d.tile_fp.reset(); d.tile_own.reset();
+    } else if (plan.prm.staged) {
         upload(d.col16, plan.col16, stream);
         d.col32.reset();
         upload(d.tile_run0, plan.tile_run0, stream);
@@ -231,6 +235,7 @@ SysDev Handle::sysdev(bool fp32) const
     s.ntiles = plan.ntiles;
     s.nrhs = nrhs;
     s.staged = plan.prm.staged ? 1 : 0;
+    s.colfmt = plan.colfmt;
     for (int c = 0; c < 4; ++c) { s.thr[c] = 0.0; s.big[c] = 1e300; }
     return s;
 }
@@ -270,7 +275,7 @@ int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 // Solve mode: stop tests up to kend = maxit.  States are initialised here.
 void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
               DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
-              int fp_bytes, int runs, bool staged, int nrhs)
+              int fp_bytes, int runs, int colfmt, int nrhs)
 {
     const int nsys = (int)sys.size();
     hipStream_t st = h.stream;
@@ -300,13 +305,13 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         JAC_HIP(hipEventRecord(h.ev[0], st));
     }
     if (h.opt.loop == 1 || nsys > 1) {
-        void* fn = sweep_kernel(fp32, nrhs, staged, true);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, true);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, nsys);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, work);
         h.last_grid = grid;
         launch_loop(fn, grid, block, lds, st, p, fp_bytes, runs, true);
     } else {
-        void* fn = sweep_kernel(fp32, nrhs, staged, false);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, false);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
         const int grid = (int)std::max<int64_t>(1, work) + 1;      // + the deciding workgroup
         h.last_grid = grid;
@@ -523,7 +528,7 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double* hist_dev)
         std::vector<SysDev> sys = {h->sysdev(false)};
         std::vector<int32_t> tb = {0, h->plan.ntiles};
         run_loop(*h, sys, false, false, nsweeps, 0, hist_dev, h->d.sys, h->d.state, h->d.tile_base, tb,
-                 h->lds_fp_bytes(false), h->lds_runs(), h->plan.prm.staged, h->nrhs);
+                 h->lds_fp_bytes(false), h->lds_runs(), h->plan.colfmt, h->nrhs);
         uint32_t which = 0;
         for (int c = 0; c < h->nrhs; ++c) which |= (uint32_t)(nsweeps % 3) << (2 * c);
         h->settle(which);
@@ -545,7 +550,7 @@ static jac_status solve64(Handle& h, double tol, int32_t maxit, int norm, int32_
     std::vector<SysDev> sys = {s};
     std::vector<int32_t> tb = {0, h.plan.ntiles};
     run_loop(h, sys, false, true, maxit, norm == JAC_NORM_INF_ABS ? 1 : 0, nullptr, h.d.sys, h.d.state,
-             h.d.tile_base, tb, h.lds_fp_bytes(false), h.lds_runs(), h.plan.prm.staged, h.nrhs);
+             h.d.tile_base, tb, h.lds_fp_bytes(false), h.lds_runs(), h.plan.colfmt, h.nrhs);
     SysState st;
     JAC_HIP(hipMemcpyAsync(&st, h.d.state.p, sizeof(SysState), hipMemcpyDeviceToHost, h.stream));
     h.sync();
@@ -584,7 +589,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         if (!(tol >= 0.0) || maxit < 0) fail(JAC_E_INVALID, "tol must be >= 0 and maxit >= 0");
         Handle& h0 = *hs[0];
         const int nrhs = h0.nrhs;
-        const bool staged = h0.plan.prm.staged;
+        const int colfmt = h0.plan.colfmt;
         std::vector<SysDev> sys;
         std::vector<int32_t> tb = {0};
         std::vector<double> scale((size_t)nsys * 4, 1.0);
@@ -592,8 +597,8 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         for (int32_t s = 0; s < nsys; ++s) {
             Handle& h = *hs[s];
             if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
-            if (h.nrhs != nrhs || h.plan.prm.staged != staged)
-                fail(JAC_E_INVALID, "all handles of a batch need the same nrhs and staging mode");
+            if (h.nrhs != nrhs || h.plan.colfmt != colfmt)
+                fail(JAC_E_INVALID, "all handles of a batch need the same nrhs and column format");
             if (h.device != h0.device) fail(JAC_E_INVALID, "all handles of a batch must be on one device");
             SysDev d = h.sysdev(false);
             for (int c = 0; c < 4; ++c) {
@@ -610,7 +615,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         for (int32_t s = 1; s < nsys; ++s) hs[s]->sync();
         upload(h0.d.batch_tile_base, tb, h0.stream);
         run_loop(h0, sys, false, true, maxit, 0, nullptr, h0.d.batch_sys, h0.d.batch_state, h0.d.batch_tile_base, tb,
-                 fpb, runs, staged, nrhs);
+                 fpb, runs, colfmt, nrhs);
         std::vector<SysState> st((size_t)nsys);
         JAC_HIP(hipMemcpyAsync(st.data(), h0.d.batch_state.p, st.size() * sizeof(SysState), hipMemcpyDeviceToHost,
                                h0.stream));
@@ -709,11 +714,11 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.ntiles = h->plan.ntiles;
         i.nslices = h->plan.nslices;
         i.max_footprint = h->plan.max_fp;
-        i.col_bytes = h->plan.prm.staged ? 2 : 4;
+        i.col_bytes = h->plan.colfmt == COL_GLOBAL32 ? 4 : 2;
         i.halo_entries = (int64_t)h->part.recv_idx.size();
         i.staged_entries = h->plan.staged_entries;
         i.alg_bytes_per_sweep = 12 * nnz + 4 * (n + 1) + 8 * n + 24 * n * r;
-        int64_t dev = h->plan.slots * (8 + i.col_bytes) + 8 * n + 24 * n * r;
+        int64_t dev = h->plan.slots * (8 + i.col_bytes) + 24 * n * r;
         dev += (int64_t)h->plan.nslices * (4 + 4 + 8);
         if (h->plan.prm.staged) dev += (h->plan.staged_entries - n) * 8 * r + (int64_t)h->plan.run_start.size() * 8;
         i.dev_bytes_per_sweep = dev;

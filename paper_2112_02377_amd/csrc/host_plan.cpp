@@ -101,6 +101,15 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
     // 3. columns per slot, entry -> slot map, diagonal slots
     pl.slot_of_nnz.assign(a.ci.size(), -1);
     pl.diag_slot.assign((size_t)n, -1);
+    bool rel16 = false;
+    if (!prm.staged && prm.rel16) {
+        int64_t maxd = 0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) maxd = std::max<int64_t>(maxd, std::abs((int64_t)a.ci[p] - i));
+        rel16 = maxd <= 32767;            // dead lanes point back to their slice's first row
+    }
+    pl.colfmt = prm.staged ? COL_LOCAL16 : (rel16 ? COL_REL16 : COL_GLOBAL32);
+    if (rel16) pl.col16.assign((size_t)pl.slots, 0);
     if (prm.staged) {
         pl.col16.assign((size_t)pl.slots, 0);
         pl.tile_run0.assign((size_t)pl.ntiles + 1, 0);
@@ -108,7 +117,7 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         pl.tile_own.assign((size_t)pl.ntiles, 0);
         pl.run_start.clear();
         pl.run_lds.clear();
-    } else {
+    } else if (!rel16) {
         pl.col32.assign((size_t)pl.slots, 0);
     }
     pl.max_fp = 0;
@@ -140,8 +149,9 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
             for (int32_t lane = 0; lane < kSlice; ++lane) {
                 const int32_t i = row0 + lane;
                 const bool live = i < r1;
-                // padding slots point at a column the tile already holds
-                const int32_t pad_global = live ? i : r0;
+                // padding slots point at a column the tile already holds: the
+                // row itself, or for lanes past the tile end the slice's first row
+                const int32_t pad_global = live ? i : row0;
                 const int32_t pad_local = live ? own + (i - r0) : own;
                 const int32_t len = live ? a.rp[i + 1] - a.rp[i] : 0;
                 for (int32_t k = 0; k < w; ++k) {
@@ -155,11 +165,15 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
                             const int32_t loc =
                                 (int32_t)(std::lower_bound(cols->begin(), cols->end(), c) - cols->begin());
                             pl.col16[slot] = (uint16_t)loc;
+                        } else if (rel16) {
+                            pl.col16[slot] = (uint16_t)(int16_t)(c - i);
                         } else {
                             pl.col32[slot] = c;
                         }
                     } else if (prm.staged) {
                         pl.col16[slot] = (uint16_t)pad_local;
+                    } else if (rel16) {
+                        pl.col16[slot] = (uint16_t)(int16_t)(pad_global - i);
                     } else {
                         pl.col32[slot] = pad_global;
                     }

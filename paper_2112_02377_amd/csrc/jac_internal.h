@@ -61,7 +61,11 @@ struct PlanParams {
     int32_t lds_elems = 4096;       // max staged x entries per tile
     int32_t max_runs = 1024;        // max footprint runs per tile
     bool staged = false;            // stage x through LDS with 16-bit local columns
+    bool rel16 = true;              // unstaged: 16-bit row-relative columns when every |j - i| fits
 };
+
+// Column index format of the sliced layout.
+enum ColFormat { COL_GLOBAL32 = 0, COL_REL16 = 1, COL_LOCAL16 = 2 };
 
 struct Plan {
     PlanParams prm;
@@ -72,8 +76,9 @@ struct Plan {
     std::vector<int32_t> slice_width; // nslices
     std::vector<int64_t> slice_off;   // nslices + 1 (slot offsets)
     int64_t slots = 0;
-    std::vector<int32_t> col32;       // slots (global columns), when !staged
-    std::vector<uint16_t> col16;      // slots (tile-local columns), when staged
+    int colfmt = COL_GLOBAL32;
+    std::vector<int32_t> col32;       // slots: global columns (COL_GLOBAL32)
+    std::vector<uint16_t> col16;      // slots: j - i as int16 (COL_REL16) or tile-local offsets (COL_LOCAL16)
     std::vector<int64_t> slot_of_nnz; // entry p of the permuted CSR -> slot
     std::vector<int64_t> diag_slot;   // new row -> slot of its diagonal
     // staging (staged only)

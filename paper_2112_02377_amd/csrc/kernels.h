@@ -18,7 +18,7 @@ struct SysDev {
     const int32_t* slice_width;
     const int64_t* slice_off;
     const int32_t* col32;     // global columns (unstaged)
-    const uint16_t* col16;    // tile-local columns (staged)
+    const uint16_t* col16;    // j - i as int16, or tile-local columns (staged)
     const int32_t* tile_run0;
     const int32_t* run_start;
     const int32_t* run_lds;
@@ -29,7 +29,7 @@ struct SysDev {
     const void* b;            // right-hand sides, T, node-major [n][nrhs]
     void* x[3];               // iterate buffers, T, node-major [n][nrhs]; x_k lives in x[k % 3]
     double* tile_part;        // [2][ntiles][nrhs] per-tile norm partials, by sweep parity
-    int32_t n, ntiles, nrhs, staged;
+    int32_t n, ntiles, nrhs, staged, colfmt;
     double thr[4];            // stop thresholds per right-hand side
     double big[4];            // divergence thresholds per right-hand side
 };

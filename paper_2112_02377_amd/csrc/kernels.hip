@@ -36,6 +36,10 @@ constexpr int SU = 4;      // staging batch
 // Pointer into global (device) memory: lets the compiler emit global_* loads.
 template <typename V>
 using gptr = __attribute__((address_space(1))) V*;
+// Pointer into memory no workgroup writes during the launch (the tile and
+// slice layout): wave-uniform reads through it become scalar loads.
+template <typename V>
+using cptr = __attribute__((address_space(4))) V*;
 
 // Coherent (device-wide) relaxed accesses for the few words workgroups of one
 // persistent launch exchange; no cache-wide maintenance is implied.
@@ -137,7 +141,7 @@ __device__ __forceinline__ void xcd_items(int32_t T, int32_t G, int32_t wg, int3
 // One tile of one sweep: stage the footprint (staged tiles), then one slice
 // of 64 rows per wavefront; accumulates the tile's residual norm partial.
 // ---------------------------------------------------------------------------
-template <typename T, int NRHS, bool STAGED>
+template <typename T, int NRHS, int CM>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
                                            bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
                                            int32_t* __restrict__ lds_ro, double (&acc)[NRHS])
@@ -146,20 +150,23 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     const gptr<const T> x = (gptr<const T>)x_;
     const gptr<T> xn = (gptr<T>)xn_;
     const gptr<const T> val = (gptr<const T>)S.val;
-    const gptr<const T> invd = (gptr<const T>)S.invd;
     const gptr<const T> b = (gptr<const T>)S.b;
     const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
     const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
-    const int32_t r0 = __builtin_amdgcn_readfirstlane(S.tile_row0[tile]);
-    const int32_t r1 = __builtin_amdgcn_readfirstlane(S.tile_row0[tile + 1]);
+    const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
+    const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
+    const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
+    const int32_t r0 = tile_row0[tile];
+    const int32_t r1 = tile_row0[tile + 1];
     int32_t own = 0;
+    constexpr bool STAGED = CM == COL_LOCAL16;
     if constexpr (STAGED) {
         const gptr<const int32_t> run_start = (gptr<const int32_t>)S.run_start;
         const gptr<const int32_t> run_lds = (gptr<const int32_t>)S.run_lds;
-        const int32_t run0 = __builtin_amdgcn_readfirstlane(S.tile_run0[tile]);
-        const int32_t nr = __builtin_amdgcn_readfirstlane(S.tile_run0[tile + 1]) - run0;
-        const int32_t fp = __builtin_amdgcn_readfirstlane(S.tile_fp[tile]);
-        own = __builtin_amdgcn_readfirstlane(S.tile_own[tile]);
+        const int32_t run0 = ((cptr<const int32_t>)S.tile_run0)[tile];
+        const int32_t nr = ((cptr<const int32_t>)S.tile_run0)[tile + 1] - run0;
+        const int32_t fp = ((cptr<const int32_t>)S.tile_fp)[tile];
+        own = ((cptr<const int32_t>)S.tile_own)[tile];
         for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) {
             lds_rs[t] = run_start[run0 + t];
             lds_ro[t] = run_lds[run0 + t];
@@ -197,37 +204,45 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         }
         __syncthreads();
     }
-    const int32_t s0 = __builtin_amdgcn_readfirstlane(S.tile_slice0[tile]);
-    const int32_t s1 = __builtin_amdgcn_readfirstlane(S.tile_slice0[tile + 1]);
+    const int32_t s0 = tile_slice0[tile];
+    const int32_t s1 = tile_slice0[tile + 1];
     // wave-uniform values kept in scalar registers
     const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t nw = (int32_t)(blockDim.x >> 6);
     const int32_t lane = threadIdx.x & 63;
     for (int32_t s = s0 + wave; s < s1; s += nw) {
-        const int32_t row0 = __builtin_amdgcn_readfirstlane(S.slice_row0[s]);
-        const int32_t w = __builtin_amdgcn_readfirstlane(S.slice_width[s]);
-        const int64_t soff = S.slice_off[s];
-        const int64_t off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(soff >> 32)) << 32) |
-                                      (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)soff)) + lane;
+        // slices are consecutive 64-row chunks of the tile; a slice's width is
+        // its slot count / 64
+        const int32_t row0 = r0 + (s - s0) * 64;
+        const int64_t soff = slice_off[s];
+        const int32_t w = (int32_t)((slice_off[s + 1] - soff) >> 6);
+        const int64_t off = soff + lane;
         const int32_t i = row0 + lane;
-        T q[NRHS];
+        T q[NRHS], xi[NRHS];
+        T d = (T)1;                               // diagonal, found among the row's entries
 #pragma unroll
-        for (int c = 0; c < NRHS; ++c) q[c] = Vec<T>::zero();
+        for (int c = 0; c < NRHS; ++c) { q[c] = Vec<T>::zero(); xi[c] = Vec<T>::zero(); }
+        const int32_t self = STAGED ? own + (i - r0) : i;   // column index of the diagonal
         for (int32_t k0 = 0; k0 < w; k0 += KB) {
+            // all value / column loads of the batch first, decoded afterwards,
+            // so that none waits for another
             T a[KB];
-            int32_t col[KB];
+            int32_t raw[KB];
 #pragma unroll
             for (int u = 0; u < KB; ++u)
                 if (k0 + u < w) {
                     const int64_t slot = off + (int64_t)(k0 + u) * 64;
                     a[u] = __builtin_nontemporal_load(&val[slot]);
-                    if constexpr (STAGED) col[u] = __builtin_nontemporal_load(&col16[slot]);
-                    else col[u] = __builtin_nontemporal_load(&col32[slot]);
+                    if constexpr (CM == COL_GLOBAL32) raw[u] = __builtin_nontemporal_load(&col32[slot]);
+                    else if constexpr (CM == COL_REL16) raw[u] = (int16_t)__builtin_nontemporal_load(&col16[slot]);
+                    else raw[u] = __builtin_nontemporal_load(&col16[slot]);
                 }
+            int32_t col[KB];
             T xv[KB][NRHS];
 #pragma unroll
             for (int u = 0; u < KB; ++u)
                 if (k0 + u < w) {
+                    col[u] = (CM == COL_REL16) ? i + raw[u] : raw[u];
 #pragma unroll
                     for (int c = 0; c < NRHS; ++c) {
                         if constexpr (STAGED) xv[u][c] = lds_x[col[u] * NRHS + c];
@@ -239,17 +254,22 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
                 if (k0 + u < w) {
 #pragma unroll
                     for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
+                    // the stored diagonal is nonzero; padding slots hold 0
+                    if (col[u] == self && a[u] != (T)0) {
+                        d = a[u];
+#pragma unroll
+                        for (int c = 0; c < NRHS; ++c) xi[c] = xv[u][c];
+                    }
                 }
         }
         if (i < r1) {
-            const T di = invd[i];
+            // D^{-1}: the correctly rounded reciprocal of the diagonal, the same
+            // value as forming it once before the iterations
+            const T di = (T)1 / d;
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) {
-                T xi;
-                if constexpr (STAGED) xi = lds_x[(own + (i - r0)) * NRHS + c];
-                else xi = x[(int64_t)i * NRHS + c];
                 const T r = b[(int64_t)i * NRHS + c] - q[c];
-                if (!((frozen >> c) & 1u)) xn[(int64_t)i * NRHS + c] = xi + di * r;
+                if (!((frozen >> c) & 1u)) xn[(int64_t)i * NRHS + c] = xi[c] + di * r;
                 const double rd = (double)r;
                 acc[c] = is_max ? maxnan(acc[c], fabs(rd)) : acc[c] + rd * rd;
             }
@@ -310,7 +330,7 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
 // One launch per sweep (single system).  Workgroups 0..ntiles-1 sweep one tile
 // each; the last workgroup takes the stop decision on the previous sweep.
 // ---------------------------------------------------------------------------
-template <typename T, int NRHS, bool STAGED>
+template <typename T, int NRHS, int CM>
 __global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
@@ -339,7 +359,7 @@ __global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t 
         double acc[NRHS];
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-        sweep_tile<T, NRHS, STAGED>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        sweep_tile<T, NRHS, CM>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -413,7 +433,7 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
     return carry;
 }
 
-template <typename T, int NRHS, bool STAGED>
+template <typename T, int NRHS, int CM>
 __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
@@ -447,7 +467,7 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
             double acc[NRHS];
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-            sweep_tile<T, NRHS, STAGED>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
+            sweep_tile<T, NRHS, CM>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
                                         reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs,
                                         lds_ro, acc);
             block_reduce<NRHS>(acc, is_max, red);
@@ -587,22 +607,30 @@ __global__ void k_colnorm_final(const double* __restrict__ part, int32_t nblocks
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T, int NRHS, bool STAGED>
+template <typename T, int NRHS, int CM>
 void* kfn(bool loop)
 {
-    return loop ? reinterpret_cast<void*>(&k_loop<T, NRHS, STAGED>) : reinterpret_cast<void*>(&k_sweep<T, NRHS, STAGED>);
+    return loop ? reinterpret_cast<void*>(&k_loop<T, NRHS, CM>) : reinterpret_cast<void*>(&k_sweep<T, NRHS, CM>);
+}
+
+template <typename T, int NRHS>
+void* pick_cm(int colfmt, bool loop)
+{
+    switch (colfmt) {
+    case COL_GLOBAL32: return kfn<T, NRHS, COL_GLOBAL32>(loop);
+    case COL_REL16: return kfn<T, NRHS, COL_REL16>(loop);
+    case COL_LOCAL16: return kfn<T, NRHS, COL_LOCAL16>(loop);
+    default: return nullptr;
+    }
 }
 
 template <typename T>
-void* pick(int nrhs, bool staged, bool loop)
+void* pick(int nrhs, int colfmt, bool loop)
 {
-    switch (nrhs * 2 + (staged ? 1 : 0)) {
-    case 2: return kfn<T, 1, false>(loop);
-    case 3: return kfn<T, 1, true>(loop);
-    case 4: return kfn<T, 2, false>(loop);
-    case 5: return kfn<T, 2, true>(loop);
-    case 8: return kfn<T, 4, false>(loop);
-    case 9: return kfn<T, 4, true>(loop);
+    switch (nrhs) {
+    case 1: return pick_cm<T, 1>(colfmt, loop);
+    case 2: return pick_cm<T, 2>(colfmt, loop);
+    case 4: return pick_cm<T, 4>(colfmt, loop);
     default: return nullptr;
     }
 }
@@ -617,9 +645,11 @@ int grid1d(int64_t m, int block = 256)
 
 }  // namespace
 
-void* sweep_kernel(bool fp32, int nrhs, bool staged, bool loop)
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, bool loop)
 {
-    return fp32 ? pick<float>(nrhs, staged, loop) : pick<double>(nrhs, staged, loop);
+    void* f = fp32 ? pick<float>(nrhs, colfmt, loop) : pick<double>(nrhs, colfmt, loop);
+    if (!f) fail(JAC_E_INVALID, "no sweep kernel for this right-hand-side count / column format");
+    return f;
 }
 
 size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys)

@@ -11,8 +11,9 @@
 namespace jac {
 
 // Kernel of the fused sweep for an element type, right-hand-side count
-// (1, 2 or 4), staging and loop kind (persistent loop or one launch per sweep).
-void* sweep_kernel(bool fp32, int nrhs, bool staged, bool loop);
+// (1, 2 or 4), column format (ColFormat) and loop kind (persistent loop or
+// one launch per sweep).
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, bool loop);
 size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys);
 void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int lds_fp_bytes,
                  int lds_runs, bool cooperative);

@@ -203,3 +203,20 @@ def test_reruns_are_bit_identical(c1):
         out.append((get_x(h, c1.n), hist))
         b.jac_destroy(h)
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_column_formats_match_oracle():
+    # 16-bit row-relative columns when every |j - i| fits, 32-bit otherwise
+    need_gpu()
+    b = B()
+    narrow = W.laplace7(9, workload=1)
+    wide = W.diffusion_system(200, 190, 2, np.full(200 * 190 * 2, 1.0), np.ones(200 * 190 * 2))
+    for s, cb in ((narrow, 2), (wide, 4)):
+        h = make(s, 1, 3)
+        assert b.jac_get_info(h)["col_bytes"] == cb
+        hist = sweep(h, 40)[:, 0]
+        _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], 40)
+        assert rel_inf(get_x(h, s.n)[0], xr) <= 1e-12
+        # b - A x carries about eps * |b_i| per row: the norm's floor is eps * ||b||
+        assert np.all(np.abs(hist - hr) <= 1e-12 * hr + 1e-14 * hr[0])
+        b.jac_destroy(h)
