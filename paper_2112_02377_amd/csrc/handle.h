@@ -48,7 +48,7 @@ struct DeviceArrays {
     DevMem sys, state, bar, bad, norm_part, bnorm;
     DevMem batch_sys, batch_state, batch_tile_base;
     // FP32 refinement
-    DevMem r32, d0, d1, rpart;
+    DevMem r32, d0, d1, d2, rpart;
     // adjoint
     DevMem t_rp, t_ci, t_map;
 };

@@ -141,11 +141,14 @@ __device__ __forceinline__ void xcd_items(int32_t T, int32_t G, int32_t wg, int3
 // One tile of one sweep: stage the footprint (staged tiles), then one slice
 // of 64 rows per wavefront; accumulates the tile's residual norm partial.
 // ---------------------------------------------------------------------------
-template <typename T, int NRHS, int CM>
+template <typename T, int NRHS, int CM, bool RESID = false>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
                                            bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
-                                           int32_t* __restrict__ lds_ro, double (&acc)[NRHS])
+                                           int32_t* __restrict__ lds_ro, double (&acc)[NRHS],
+                                           float* rout_ = nullptr)
 {
+    // RESID: no update; the residual is written rounded to FP32 into rout
+    const gptr<float> rout = (gptr<float>)rout_;
     // every array below is device memory: global address space for the loads
     const gptr<const T> x = (gptr<const T>)x_;
     const gptr<T> xn = (gptr<T>)xn_;
@@ -269,7 +272,8 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) {
                 const T r = b[(int64_t)i * NRHS + c] - q[c];
-                if (!((frozen >> c) & 1u)) xn[(int64_t)i * NRHS + c] = xi[c] + di * r;
+                if constexpr (RESID) rout[(int64_t)i * NRHS + c] = ((frozen >> c) & 1u) ? 0.0f : (float)r;
+                else if (!((frozen >> c) & 1u)) xn[(int64_t)i * NRHS + c] = xi[c] + di * r;
                 const double rd = (double)r;
                 acc[c] = is_max ? maxnan(acc[c], fabs(rd)) : acc[c] + rd * rd;
             }
@@ -374,6 +378,75 @@ __global__ void __launch_bounds__(512) k_decide(LoopParams P, int32_t k)
 {
     __shared__ double red[16 * 4];
     decide<NRHS, false>(P, 0, k, P.sys[0], red);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual for mixed-precision refinement: r = b - A x with the FP64
+// coefficients, written as FP32 (the right-hand side of the inner FP32
+// sweeps; columns in `frozen` get 0), plus the FP64 norm partial per tile.
+// ---------------------------------------------------------------------------
+template <int NRHS, int CM>
+__global__ void __launch_bounds__(512) k_resid(const SysDev* sys, float* r32, uint32_t frozen, int32_t norm_inf,
+                                              int32_t lds_fp_bytes, int32_t lds_runs)
+{
+    extern __shared__ __align__(16) char smem[];
+    const SysDev& S = *sys;
+    double* lds_x = reinterpret_cast<double*>(smem);
+    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    int32_t* lds_ro = lds_rs + lds_runs;
+    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t first, end, stride;
+    xcd_items(S.ntiles, gridDim.x, blockIdx.x, first, end, stride);
+    const bool is_max = norm_inf != 0;
+    for (int32_t tile = first; tile < end; tile += stride) {
+        double acc[NRHS];
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
+        sweep_tile<double, NRHS, CM, true>(S, tile, reinterpret_cast<const double*>(S.x[0]), nullptr, frozen,
+                                           is_max, lds_x, lds_rs, lds_ro, acc, r32);
+        block_reduce<NRHS>(acc, is_max, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) S.tile_part[(int64_t)tile * NRHS + c] = acc[c];
+        }
+    }
+}
+
+// Norms of the per-tile partials (tile order), one block.
+template <int NRHS>
+__global__ void __launch_bounds__(256) k_part_norm(const SysDev* sys, int32_t norm_inf, double* out)
+{
+    __shared__ double red[16 * 4];
+    const SysDev& S = *sys;
+    const bool is_max = norm_inf != 0;
+    double v[NRHS];
+#pragma unroll
+    for (int c = 0; c < NRHS; ++c) v[c] = 0.0;
+    for (int32_t t = threadIdx.x; t < S.ntiles; t += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c) {
+            const double p = S.tile_part[(int64_t)t * NRHS + c];
+            v[c] = is_max ? maxnan(v[c], p) : v[c] + p;
+        }
+    block_reduce<NRHS>(v, is_max, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c) out[c] = is_max ? v[c] : sqrt(v[c]);
+}
+
+// x += (double) d for the columns in `active`; which[c] (2 bits) names the
+// inner buffer holding column c's correction.
+__global__ void k_add_correction(double* __restrict__ x, const float* __restrict__ d0, const float* __restrict__ d1,
+                                 const float* __restrict__ d2, int32_t n, int32_t nrhs, uint32_t which,
+                                 uint32_t active)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        for (int c = 0; c < nrhs; ++c) {
+            if (!((active >> c) & 1u)) continue;
+            const uint32_t w = (which >> (2 * c)) & 3u;
+            const float* d = w == 0 ? d0 : (w == 1 ? d1 : d2);
+            x[(int64_t)i * nrhs + c] += (double)d[(int64_t)i * nrhs + c];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,6 +754,42 @@ void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k)
     case 2: k_decide<2><<<1, 256, 0, st>>>(p, k); break;
     default: k_decide<4><<<1, 256, 0, st>>>(p, k); break;
     }
+    JAC_HIP(hipGetLastError());
+}
+
+template <int NRHS>
+void* resid_fn(int colfmt)
+{
+    switch (colfmt) {
+    case COL_GLOBAL32: return reinterpret_cast<void*>(&k_resid<NRHS, COL_GLOBAL32>);
+    case COL_REL16: return reinterpret_cast<void*>(&k_resid<NRHS, COL_REL16>);
+    default: return reinterpret_cast<void*>(&k_resid<NRHS, COL_LOCAL16>);
+    }
+}
+
+void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
+                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs)
+{
+    void* fn = nrhs == 1 ? resid_fn<1>(colfmt) : (nrhs == 2 ? resid_fn<2>(colfmt) : resid_fn<4>(colfmt));
+    int32_t ni = norm_inf;
+    void* args[] = {&sys, &r32, &frozen, &ni, &lds_fp_bytes, &lds_runs};
+    JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
+}
+
+void launch_part_norm(int nrhs, hipStream_t st, const SysDev* sys, int norm_inf, double* out)
+{
+    switch (nrhs) {
+    case 1: k_part_norm<1><<<1, 256, 0, st>>>(sys, norm_inf, out); break;
+    case 2: k_part_norm<2><<<1, 256, 0, st>>>(sys, norm_inf, out); break;
+    default: k_part_norm<4><<<1, 256, 0, st>>>(sys, norm_inf, out); break;
+    }
+    JAC_HIP(hipGetLastError());
+}
+
+void launch_add_correction(double* x, const float* d0, const float* d1, const float* d2, int32_t n, int32_t nrhs,
+                           uint32_t which, uint32_t active, hipStream_t st)
+{
+    if (n > 0 && active) k_add_correction<<<grid1d(n), 256, 0, st>>>(x, d0, d1, d2, n, nrhs, which, active);
     JAC_HIP(hipGetLastError());
 }
 

@@ -20,6 +20,12 @@ void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, Loop
 void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
                    int lds_fp_bytes, int lds_runs);
 void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k);
+// mixed-precision refinement
+void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
+                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs);
+void launch_part_norm(int nrhs, hipStream_t st, const SysDev* sys, int norm_inf, double* out);
+void launch_add_correction(double* x, const float* d0, const float* d1, const float* d2, int32_t n, int32_t nrhs,
+                           uint32_t which, uint32_t active, hipStream_t st);
 
 void launch_scatter_vals(const double* vals, const int32_t* slot_of, int64_t nnz, double* out, hipStream_t st);
 void launch_invd(const double* val, const int32_t* diag_slot, int32_t n, double* invd, float* invd32, int32_t* bad,
