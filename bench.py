@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--loop", type=int, default=0, help="0 = one launch per sweep, 1 = persistent loop")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -120,6 +121,8 @@ def main():
             B.jac_set_option(h, B.JAC_OPT_TILE_ROWS, args.tile_rows)
         if args.block:
             B.jac_set_option(h, B.JAC_OPT_BLOCK, args.block)
+        if args.wg_per_cu:
+            B.jac_set_option(h, B.JAC_OPT_WG_PER_CU, args.wg_per_cu)
         B.jac_set_grid(h, N, N, N)
         B.jac_partition(h, mode, P, sub)
         B.jac_set_option(h, B.JAC_OPT_TIMING, 1)

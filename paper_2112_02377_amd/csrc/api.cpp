@@ -283,8 +283,8 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     JAC_HIP(hipMemcpyAsync(d_sys.p, sys.data(), sys.size() * sizeof(SysDev), hipMemcpyHostToDevice, st));
     if (d_state.bytes < sys.size() * sizeof(SysState)) d_state.alloc(sys.size() * sizeof(SysState));
     launch_init_state(static_cast<SysState*>(d_state.p), nsys, st);
-    if (!h.d.bar.p) h.d.bar.alloc(16);
-    launch_zero_u32(static_cast<uint32_t*>(h.d.bar.p), 4, st);
+    if (!h.d.bar.p) h.d.bar.alloc(4096);
+    launch_zero_u32(static_cast<uint32_t*>(h.d.bar.p), 1024, st);
     LoopParams p{};
     p.sys = static_cast<const SysDev*>(d_sys.p);
     p.st = static_cast<SysState*>(d_state.p);

@@ -287,7 +287,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
 // where other workgroups of the same launch wrote the partials) or plain ones
 // (a later launch: the kernel boundary made them visible).
 template <int NRHS, bool DEV>
-__device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& S, double* red)
+__device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& S, double* red, int32_t lag = 1)
 {
     SysState* st = &P.st[s];
     if (ldv<DEV>(&st->done_k) <= k) return;                 // already decided (launches past the stop)
@@ -326,7 +326,10 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
             stv<DEV>(&st->status, (int32_t)JAC_NOT_CONVERGED);
         }
         stv<DEV>(&st->last_k, k);
-        if (!running && P.solve) stv<DEV>(&st->done_k, k + 1);
+        // the system leaves the work list from sweep k + lag on: launches
+        // (lag 1) see it from launch k + 1; the persistent loop (lag 2) takes
+        // the decision during sweep k + 1, so sweep k + 1 still runs for all
+        if (!running && P.solve) stv<DEV>(&st->done_k, k + lag);
     }
 }
 
@@ -452,24 +455,36 @@ __global__ void k_add_correction(double* __restrict__ x, const float* __restrict
 // ---------------------------------------------------------------------------
 // Persistent loop: every sweep of every system in one cooperative launch.
 // ---------------------------------------------------------------------------
+// Grid barrier with a two-level combining tree (eight group counters, one
+// top counter, one generation word, each on its own 128-byte line) so that
+// arrivals do not all serialise on one address.  Every workgroup releases its
+// writes device-wide before arriving and acquires after the release.
+constexpr int kBarStride = 32;   // uint32 words between barrier counters (10 used)
+
 __device__ void grid_barrier(uint32_t* bar, uint32_t G)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t* count = bar;
-        uint32_t* gen = bar + 1;
+        uint32_t* gen = bar + 9 * kBarStride;
+        uint32_t* top = bar + 8 * kBarStride;
         const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // release this workgroup's iterate writes device-wide
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == G - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0)
-                __builtin_amdgcn_s_sleep(1);
+        const uint32_t ngroups = G < 8 ? G : 8;
+        const uint32_t grp = blockIdx.x & 7;
+        const uint32_t gsize = (G - grp + 7) >> 3;
+        uint32_t* cnt = bar + grp * kBarStride;
+        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gsize - 1) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const uint32_t t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
-        // acquire the other workgroups' writes
+        while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(2);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -506,6 +521,12 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
     return carry;
 }
 
+// Each sweep: (A) workgroup s mod G takes the stop decision of system s on
+// the previous sweep (its partials were released by the last barrier);
+// (B) every workgroup builds the same work list (a system decided during
+// sweep k leaves it from sweep k+2, so a racing read cannot change the list);
+// (C) tiles; (D) barrier.  The third iterate buffer keeps x_k intact while
+// sweep k+1 runs before the decision on r_k is known.
 template <typename T, int NRHS, int CM>
 __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t lds_runs)
 {
@@ -520,6 +541,9 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
     const int32_t G = gridDim.x;
     const bool is_max = P.norm_inf != 0;
     for (int32_t k = P.k0;; ++k) {
+        if (k > P.k0)
+            for (int32_t s = blockIdx.x; s < P.nsys; s += G)
+                if (P.st[s].done_k == kRunning) decide<NRHS, false>(P, s, k - 1, P.sys[s], red, 2);
         if (!P.solve && k >= P.kend) break;
         const int32_t T_act = build_work(P, k, pref, wsum);
         if (T_act == 0) break;
@@ -533,7 +557,7 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
             }
             const int32_t sidx = lo, tile = j - pref[lo];
             const SysDev& S = P.sys[sidx];
-            SysState* sst = &P.st[sidx];
+            const SysState* sst = &P.st[sidx];
             uint32_t frozen = 0;
             for (int c = 0; c < NRHS; ++c)
                 if (ld_dev(&sst->stop_k[c]) < k) frozen |= 1u << c;
@@ -541,26 +565,13 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
             sweep_tile<T, NRHS, CM>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
-                                        reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs,
-                                        lds_ro, acc);
+                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs, lds_ro,
+                                    acc);
             block_reduce<NRHS>(acc, is_max, red);
             if (threadIdx.x == 0) {
                 double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
 #pragma unroll
-                for (int c = 0; c < NRHS; ++c) st_dev(&part[(int64_t)tile * NRHS + c], acc[c]);
-                // the partial is complete device-wide before the arrival counts it
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                const uint32_t old =
-                    __hip_atomic_fetch_add(&sst->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *flag = (old == (uint32_t)S.ntiles - 1u) ? 1 : 0;
-            }
-            __syncthreads();
-            const bool last = *flag != 0;
-            __syncthreads();
-            if (last) {
-                decide<NRHS, true>(P, sidx, k, S, red);
-                if (threadIdx.x == 0)
-                    __hip_atomic_store(&sst->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int c = 0; c < NRHS; ++c) part[(int64_t)tile * NRHS + c] = acc[c];
             }
         }
         grid_barrier(P.bar, (uint32_t)G);
