@@ -1,0 +1,244 @@
+// Reverse-mode derivative of K synchronous Jacobi sweeps from x_0 = 0.
+//
+// One sweep is x_{k+1,i} = x_{k,i} + (b_i - sum_j a_ij x_{k,j}) / a_ii (paper
+// section 3, correction form).  Given lambda_K = dL/dx_K, with
+// mu_{k+1} = D^{-1} lambda_{k+1}, for k = K-1 down to 0:
+//   lambda_k  = lambda_{k+1} - A^T mu_{k+1}
+//   dL/db    += mu_{k+1}
+//   dL/da_ij -= mu_{k+1,i} x_{k,j}      (j != i)
+//   dL/da_ii -= mu_{k+1,i} x_{k+1,i}    (through both A x_k and 1/a_ii)
+// The iterates are kept only every ckpt_every sweeps.  Each segment is swept
+// again from its checkpoint with the same kernel (bit-identical iterates),
+// then reversed step by step on A^T, and its dL/dvals contributions are added
+// in one pass over A's stored entries.
+#include <algorithm>
+#include <cstring>
+
+#include "handle.h"
+#include "launch.h"
+
+namespace jac {
+
+// Sliced layout of A^T (of the permuted system) and the map from each of its
+// slots to the slot of the same entry of A.
+static void build_transpose(Handle& h)
+{
+    Csr pat;
+    pat.n = h.a.n;
+    pat.rp = h.a.rp;
+    pat.ci = h.a.ci;
+    Csr pa = permute(pat, h.part.perm, h.part.iperm, nullptr);
+    const int32_t n = pa.n;
+    Csr at;
+    at.n = n;
+    at.rp.assign((size_t)n + 1, 0);
+    for (int64_t q = 0; q < pa.nnz(); ++q) at.rp[pa.ci[q] + 1]++;
+    for (int32_t i = 0; i < n; ++i) at.rp[i + 1] += at.rp[i];
+    at.ci.resize(pa.ci.size());
+    std::vector<int64_t> from(pa.ci.size());            // A^T entry -> A (permuted) entry
+    std::vector<int32_t> fill(at.rp.begin(), at.rp.end() - 1);
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t q = pa.rp[r]; q < pa.rp[r + 1]; ++q) {
+            const int32_t e = fill[pa.ci[q]]++;
+            at.ci[e] = r;                                  // rows visited ascending: columns ascend
+            from[e] = q;
+        }
+    PlanParams prm;
+    prm.tile_rows = h.opt.tile_rows;
+    prm.staged = false;
+    h.tplan = make_plan(at, {0, n}, prm);
+    // A's plan was built on the same permuted matrix: its slot of entry q
+    std::vector<int32_t> mapT((size_t)h.tplan.slots, -1);
+    for (size_t e = 0; e < from.size(); ++e) mapT[h.tplan.slot_of_nnz[e]] = (int32_t)h.plan.slot_of_nnz[from[e]];
+    auto up = [&](DevMem& m, const void* p, size_t nb) {
+        m.alloc(nb);
+        if (nb) JAC_HIP(hipMemcpyAsync(m.p, p, nb, hipMemcpyHostToDevice, h.stream));
+    };
+    const Plan& t = h.tplan;
+    up(h.td.tile_row0, t.tile_row0.data(), t.tile_row0.size() * 4);
+    up(h.td.tile_slice0, t.tile_slice0.data(), t.tile_slice0.size() * 4);
+    up(h.td.slice_off, t.slice_off.data(), t.slice_off.size() * 8);
+    if (t.colfmt == COL_REL16) up(h.td.col16, t.col16.data(), t.col16.size() * 2);
+    else up(h.td.col32, t.col32.data(), t.col32.size() * 4);
+    up(h.td.t_map, mapT.data(), mapT.size() * 4);
+    h.td.val.alloc((size_t)t.slots * sizeof(double));
+    // The gradient pass reads x at global columns of A's slots: a staged plan
+    // stores tile-local offsets, so rebuild the global column of every slot
+    // from the tile's footprint runs.
+    const Plan& pl = h.plan;
+    if (pl.colfmt == COL_LOCAL16) {
+        std::vector<int32_t> gcol((size_t)pl.slots, 0);
+        for (int32_t tt = 0; tt < pl.ntiles; ++tt) {
+            const int32_t ra = pl.tile_run0[tt], rb = pl.tile_run0[tt + 1];
+            for (int32_t sl = pl.tile_slice0[tt]; sl < pl.tile_slice0[tt + 1]; ++sl)
+                for (int64_t q = pl.slice_off[sl]; q < pl.slice_off[sl + 1]; ++q) {
+                    const int32_t loc = pl.col16[q];
+                    int32_t r = ra;                       // last run starting at or before loc
+                    while (r + 1 < rb && pl.run_lds[r + 1] <= loc) ++r;
+                    gcol[q] = pl.run_start[r] + (loc - pl.run_lds[r]);
+                }
+        }
+        up(h.td.a_gcol, gcol.data(), gcol.size() * 4);
+    } else {
+        h.td.a_gcol.reset();
+    }
+    h.sync();
+    h.have_t = true;
+}
+
+static void sweep_fixed(Handle& h, int32_t K)
+{
+    if (K <= 0) return;
+    std::vector<SysDev> sys = {h.sysdev(false)};
+    std::vector<int32_t> tb = {0, h.plan.ntiles};
+    run_loop(h, sys, false, false, K, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, h.lds_fp_bytes(false),
+             h.lds_runs(), h.plan.colfmt, h.nrhs);
+    uint32_t which = 0;
+    for (int c = 0; c < h.nrhs; ++c) which |= (uint32_t)(K % 3) << (2 * c);
+    h.settle(which);
+}
+
+}  // namespace jac
+
+using namespace jac;
+
+extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const double* gx_dev, double* gb_dev,
+                                  double* gvals_dev)
+{
+    try {
+        if (!hp || !gx_dev) fail(JAC_E_INVALID, "NULL argument");
+        Handle& h = *hp;
+        if (K < 0 || ckpt < 1) fail(JAC_E_INVALID, "need K >= 0 and ckpt_every >= 1");
+        if (h.nrhs != 1) fail(JAC_E_INVALID, "jac_adjoint needs a handle with one right-hand side");
+        const int32_t n = h.a.n;
+        const int64_t nnz = h.a.nnz();
+        const hipStream_t st = h.stream;
+        const int32_t c = std::max(1, std::min(ckpt, std::max(K, 1)));
+        const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
+        const size_t vec = (size_t)n * sizeof(double);
+        const size_t need = (size_t)nseg * vec + (size_t)(2 * c + 1) * vec + 4 * vec + (size_t)h.plan.slots * 8;
+        if (need > (size_t)h.opt.ckpt_mb << 20)
+            fail(JAC_E_INVALID, "adjoint buffers exceed JAC_OPT_CKPT_MEM_MB; raise it or the checkpoint stride");
+        if (!h.have_t) build_transpose(h);
+        // A^T values from A's slots (coefficients may have changed since)
+        launch_fill_mapped(static_cast<const double*>(h.d.val.p), static_cast<const int32_t*>(h.td.t_map.p),
+                           h.tplan.slots, static_cast<double*>(h.td.val.p), st);
+        SysDev sT{};
+        sT.tile_row0 = static_cast<const int32_t*>(h.td.tile_row0.p);
+        sT.tile_slice0 = static_cast<const int32_t*>(h.td.tile_slice0.p);
+        sT.slice_off = static_cast<const int64_t*>(h.td.slice_off.p);
+        sT.col32 = static_cast<const int32_t*>(h.td.col32.p);
+        sT.col16 = static_cast<const uint16_t*>(h.td.col16.p);
+        sT.val = h.td.val.p;
+        sT.n = n;
+        sT.ntiles = h.tplan.ntiles;
+        sT.nrhs = 1;
+        sT.colfmt = h.tplan.colfmt;
+        DevMem d_sT, d_sA;
+        d_sT.alloc(sizeof(SysDev));
+        JAC_HIP(hipMemcpyAsync(d_sT.p, &sT, sizeof(SysDev), hipMemcpyHostToDevice, st));
+        SysDev sA = h.sysdev(false);
+        SysDev sG = sA;                       // A's layout with global columns, for the gradient
+        int gfmt = h.plan.colfmt;
+        if (gfmt == COL_LOCAL16) {
+            sG.col32 = static_cast<const int32_t*>(h.td.a_gcol.p);
+            gfmt = COL_GLOBAL32;
+        }
+        DevMem d_sG;
+        d_sG.alloc(sizeof(SysDev));
+        JAC_HIP(hipMemcpyAsync(d_sG.p, &sG, sizeof(SysDev), hipMemcpyHostToDevice, st));
+        d_sA.alloc(sizeof(SysDev));
+        JAC_HIP(hipMemcpyAsync(d_sA.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
+        JAC_HIP(hipStreamSynchronize(st));   // host structs are temporaries
+
+        DevMem ck, X, M, lam0, lam1, carry, gb, G;
+        ck.alloc(std::max<size_t>((size_t)nseg * vec, 16));
+        X.alloc((size_t)(c + 1) * vec);
+        M.alloc((size_t)c * vec);
+        lam0.alloc(vec);
+        lam1.alloc(vec);
+        carry.alloc(vec);
+        gb.alloc(vec);
+        G.alloc((size_t)h.plan.slots * 8);
+        JAC_HIP(hipMemsetAsync(G.p, 0, (size_t)h.plan.slots * 8, st));
+        JAC_HIP(hipMemsetAsync(gb.p, 0, vec, st));
+        auto Xm = [&](int m) { return static_cast<double*>(X.p) + (size_t)m * n; };
+        auto Mm = [&](int m) { return static_cast<double*>(M.p) + (size_t)m * n; };
+        auto CK = [&](int j) { return static_cast<double*>(ck.p) + (size_t)j * n; };
+
+        // forward with checkpoints, from x_0 = 0
+        launch_gather_in(nullptr, static_cast<const int32_t*>(h.d.perm.p), n, 1, static_cast<double*>(h.d.x0.p), st);
+        for (int32_t j = 0; j < nseg; ++j) {
+            JAC_HIP(hipMemcpyAsync(CK(j), h.d.x0.p, vec, hipMemcpyDeviceToDevice, st));
+            sweep_fixed(h, std::min(c, K - j * c));
+        }
+        if (K > 0) {
+            // lambda_K (internal order), mu_K = D^{-1} lambda_K, gb = mu_K
+            launch_gather_in(gx_dev, static_cast<const int32_t*>(h.d.perm.p), n, 1, static_cast<double*>(lam0.p),
+                             st);
+            const int32_t Llast = K - (nseg - 1) * c;
+            launch_adj_init(static_cast<const double*>(h.d.invd.p), static_cast<const double*>(lam0.p), n,
+                            Mm(Llast - 1), static_cast<double*>(gb.p), st);
+            // one-sweep kernels that read X[m] and write X[m+1]
+            std::vector<SysDev> segs((size_t)c);
+            DevMem d_segs;
+            d_segs.alloc(sizeof(SysDev) * (size_t)c);
+            void* fn = sweep_kernel(false, 1, h.plan.colfmt, false);
+            const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
+            const size_t lds = loop_lds_bytes(fpb, runs, 0);
+            const int grid = std::max(h.plan.ntiles, 1) + 1;
+            launch_init_state(static_cast<SysState*>(h.d.state.p), 1, st);
+            double* lin = static_cast<double*>(lam0.p);
+            double* lout = static_cast<double*>(lam1.p);
+            for (int32_t j = nseg - 1; j >= 0; --j) {
+                const int32_t k0 = j * c;
+                const int32_t L = std::min(c, K - k0);
+                JAC_HIP(hipMemcpyAsync(Xm(0), CK(j), vec, hipMemcpyDeviceToDevice, st));
+                for (int32_t m = 0; m < L; ++m) {
+                    segs[m] = sA;
+                    segs[m].x[0] = Xm(m);
+                    segs[m].x[1] = Xm(m + 1);
+                    segs[m].x[2] = Xm(m + 1);
+                }
+                JAC_HIP(hipMemcpyAsync(d_segs.p, segs.data(), sizeof(SysDev) * (size_t)L, hipMemcpyHostToDevice, st));
+                JAC_HIP(hipStreamSynchronize(st));
+                for (int32_t m = 0; m < L; ++m) {
+                    LoopParams p{};
+                    p.sys = static_cast<const SysDev*>(d_segs.p) + m;
+                    p.st = static_cast<SysState*>(h.d.state.p);
+                    p.nsys = 1;
+                    p.k0 = 0;
+                    p.kend = 1;
+                    p.solve = 0;
+                    launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, runs);
+                }
+                for (int32_t m = L - 1; m >= 0; --m) {
+                    const int32_t k = k0 + m;
+                    double* mu_out = nullptr;
+                    if (k >= 1) mu_out = m >= 1 ? Mm(m - 1) : static_cast<double*>(carry.p);
+                    launch_adj_step(h.tplan.colfmt, h.tplan.ntiles, st, static_cast<const SysDev*>(d_sT.p), lin,
+                                    Mm(m), lout, mu_out, static_cast<double*>(gb.p),
+                                    static_cast<const double*>(h.d.invd.p));
+                    std::swap(lin, lout);
+                }
+                launch_adj_grad(gfmt, h.plan.ntiles, st, static_cast<const SysDev*>(d_sG.p), Xm(0), Mm(0), L,
+                                static_cast<double*>(G.p));
+                if (j > 0) JAC_HIP(hipMemcpyAsync(Mm(c - 1), carry.p, vec, hipMemcpyDeviceToDevice, st));
+            }
+        }
+        if (gb_dev)
+            launch_scatter_out(static_cast<const double*>(gb.p), static_cast<const int32_t*>(h.d.perm.p), n, 1, gb_dev,
+                               st);
+        if (gvals_dev)
+            launch_fill_mapped(static_cast<const double*>(G.p), static_cast<const int32_t*>(h.d.slot_of_caller.p), nnz,
+                               gvals_dev, st);
+        h.sync();
+        return JAC_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return JAC_E_NOMEM;
+    }
+}

@@ -109,6 +109,7 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     sync();
     part = std::move(np);
     plan = std::move(pl);
+    have_t = false;                 // the transposed layout follows the split
     upload(d.tile_row0, plan.tile_row0, stream);
     upload(d.tile_slice0, plan.tile_slice0, stream);
     upload(d.slice_row0, plan.slice_row0, stream);
@@ -281,6 +282,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     hipStream_t st = h.stream;
     if (d_sys.bytes < sys.size() * sizeof(SysDev)) d_sys.alloc(sys.size() * sizeof(SysDev));
     JAC_HIP(hipMemcpyAsync(d_sys.p, sys.data(), sys.size() * sizeof(SysDev), hipMemcpyHostToDevice, st));
+    JAC_HIP(hipStreamSynchronize(st));   // the host array is a temporary
     if (d_state.bytes < sys.size() * sizeof(SysState)) d_state.alloc(sys.size() * sizeof(SysState));
     launch_init_state(static_cast<SysState*>(d_state.p), nsys, st);
     if (!h.d.bar.p) h.d.bar.alloc(4096);
@@ -408,9 +410,9 @@ jac_status jac_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                                    h->stream));
         else
             JAC_HIP(hipMemsetAsync(h->d.b_caller.p, 0, (size_t)n * nrhs * sizeof(double), h->stream));
-        h->a.v.clear();
+        h->replan(JAC_BANDROW, 1, nullptr);   // ends with a stream synchronisation
+        h->a.v.clear();                      // values now live on the device only
         h->a.v.shrink_to_fit();
-        h->replan(JAC_BANDROW, 1, nullptr);
         *out = h.release();
         return JAC_OK;
     });

@@ -1,13 +1,8 @@
-// Entry points still under construction: the adjoint and the autotuner.
+// Entry points still under construction: the autotuner.
 #include "handle.h"
 
 
 extern "C" {
-jac_status jac_adjoint(jac_handle, int32_t, int32_t, const double*, double*, double*)
-{
-    jac::set_last_error("jac_adjoint is not available in this build");
-    return JAC_E_INVALID;
-}
 jac_status jac_autotune(jac_handle, int32_t)
 {
     jac::set_last_error("jac_autotune is not available in this build");

@@ -50,7 +50,7 @@ struct DeviceArrays {
     // FP32 refinement
     DevMem r32, d0, d1, d2, rpart;
     // adjoint
-    DevMem t_rp, t_ci, t_map;
+    DevMem t_map, a_gcol;
 };
 
 struct Handle {

@@ -864,3 +864,186 @@ void launch_colnorm(const double* b, int32_t n, int32_t nrhs, double* part /*[25
 }
 
 }  // namespace jac
+
+// ===========================================================================
+// Reverse-mode derivative of K sweeps (adjoint).
+//
+// One sweep is x_{k+1,i} = x_{k,i} + (b_i - sum_j a_ij x_{k,j}) / a_ii.  With
+// lambda_K = dL/dx_K and mu_{k+1} = D^{-1} lambda_{k+1}, for k = K-1 .. 0:
+//   lambda_k = lambda_{k+1} - A^T mu_{k+1}
+//   dL/db   += mu_{k+1}
+//   dL/da_ij -= mu_{k+1,i} x_{k,j}   (j != i),   dL/da_ii -= mu_{k+1,i} x_{k+1,i}
+// ===========================================================================
+namespace jac {
+namespace {
+
+// mu = D^{-1} lambda; gb = mu (the first reverse step's contribution).
+__global__ void k_adj_init(const double* __restrict__ invd, const double* __restrict__ lam, int32_t n,
+                           double* __restrict__ mu, double* __restrict__ gb)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double m = invd[i] * lam[i];
+        mu[i] = m;
+        gb[i] = m;
+    }
+}
+
+// One reverse step on the sliced layout of A^T: lam_out = lam_in - A^T mu;
+// when mu_out is given, also mu_out = D^{-1} lam_out and gb += mu_out.
+template <int CM>
+__global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const double* __restrict__ lam_in,
+                                                 const double* __restrict__ mu_, double* __restrict__ lam_out,
+                                                 double* __restrict__ mu_out, double* __restrict__ gb,
+                                                 const double* __restrict__ invd)
+{
+    const SysDev& S = *sysT;
+    const gptr<const double> val = (gptr<const double>)S.val;
+    const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
+    const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
+    const gptr<const double> mu = (gptr<const double>)mu_;
+    const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
+    const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
+    const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
+    int32_t first, end, stride;
+    xcd_items(S.ntiles, gridDim.x, blockIdx.x, first, end, stride);
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    const int32_t lane = threadIdx.x & 63;
+    for (int32_t tile = first; tile < end; tile += stride) {
+        const int32_t r0 = tile_row0[tile], r1 = tile_row0[tile + 1];
+        const int32_t s0 = tile_slice0[tile], s1 = tile_slice0[tile + 1];
+        for (int32_t s = s0 + wave; s < s1; s += nw) {
+            const int32_t row0 = r0 + (s - s0) * 64;
+            const int64_t soff = slice_off[s];
+            const int32_t w = (int32_t)((slice_off[s + 1] - soff) >> 6);
+            const int64_t off = soff + lane;
+            const int32_t i = row0 + lane;
+            double q = 0.0;
+            for (int32_t k0 = 0; k0 < w; k0 += KB) {
+                double a[KB];
+                int32_t raw[KB];
+#pragma unroll
+                for (int u = 0; u < KB; ++u)
+                    if (k0 + u < w) {
+                        const int64_t slot = off + (int64_t)(k0 + u) * 64;
+                        a[u] = __builtin_nontemporal_load(&val[slot]);
+                        if constexpr (CM == COL_GLOBAL32) raw[u] = __builtin_nontemporal_load(&col32[slot]);
+                        else raw[u] = (int16_t)__builtin_nontemporal_load(&col16[slot]);
+                    }
+                double mv[KB];
+#pragma unroll
+                for (int u = 0; u < KB; ++u)
+                    if (k0 + u < w) mv[u] = mu[(CM == COL_REL16) ? i + raw[u] : raw[u]];
+#pragma unroll
+                for (int u = 0; u < KB; ++u)
+                    if (k0 + u < w) q = __builtin_fma(a[u], mv[u], q);
+            }
+            if (i < r1) {
+                const double l = lam_in[i] - q;
+                lam_out[i] = l;
+                if (mu_out) {
+                    const double m = invd[i] * l;
+                    mu_out[i] = m;
+                    gb[i] += m;
+                }
+            }
+        }
+    }
+}
+
+// Gradient of one segment, on A's sliced layout (SDDMM form): for every slot
+// (row i, column j) of A, G -= sum_m mu[m][i] * (j == i ? x[m+1][i] : x[m][j]),
+// m ascending.  mu[m] = mu_{k0+m+1}, x[m] = x_{k0+m}; both node-major
+// [m][n] (m-th vector at offset m*n).
+template <int CM>
+__global__ void __launch_bounds__(512) k_adj_grad(const SysDev* sysA, const double* __restrict__ X,
+                                                 const double* __restrict__ M, int32_t L, double* __restrict__ G)
+{
+    const SysDev& S = *sysA;
+    const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
+    const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
+    const gptr<const double> Xg = (gptr<const double>)X;
+    const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
+    const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
+    const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
+    const int64_t n = S.n;
+    int32_t first, end, stride;
+    xcd_items(S.ntiles, gridDim.x, blockIdx.x, first, end, stride);
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    const int32_t lane = threadIdx.x & 63;
+    for (int32_t tile = first; tile < end; tile += stride) {
+        const int32_t r0 = tile_row0[tile], r1 = tile_row0[tile + 1];
+        const int32_t s0 = tile_slice0[tile], s1 = tile_slice0[tile + 1];
+        for (int32_t s = s0 + wave; s < s1; s += nw) {
+            const int32_t row0 = r0 + (s - s0) * 64;
+            const int64_t soff = slice_off[s];
+            const int32_t w = (int32_t)((slice_off[s + 1] - soff) >> 6);
+            const int32_t i = row0 + lane;
+            if (i >= r1) continue;
+            for (int32_t kk = 0; kk < w; ++kk) {
+                const int64_t slot = soff + (int64_t)kk * 64 + lane;
+                int32_t j;
+                if constexpr (CM == COL_GLOBAL32) j = col32[slot];
+                else j = i + (int32_t)(int16_t)col16[slot];
+                const bool diag = (j == i);
+                double acc = 0.0;
+                for (int32_t m = 0; m < L; ++m) {
+                    const double xv = diag ? Xg[(int64_t)(m + 1) * n + i] : Xg[(int64_t)m * n + j];
+                    acc = __builtin_fma(M[(int64_t)m * n + i], xv, acc);
+                }
+                G[slot] -= acc;
+            }
+        }
+    }
+}
+
+__global__ void k_fill_mapped(const double* __restrict__ src, const int32_t* __restrict__ map, int64_t m,
+                              double* __restrict__ dst)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t q = map[p];
+        dst[p] = q >= 0 ? src[q] : 0.0;
+    }
+}
+
+}  // namespace
+
+void launch_adj_init(const double* invd, const double* lam, int32_t n, double* mu, double* gb, hipStream_t st)
+{
+    if (n > 0) k_adj_init<<<grid1d(n), 256, 0, st>>>(invd, lam, n, mu, gb);
+    JAC_HIP(hipGetLastError());
+}
+
+void launch_adj_step(int colfmt, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
+                     const double* mu, double* lam_out, double* mu_out, double* gb, const double* invd)
+{
+    // global or row-relative columns only: tile-local offsets need the staged footprint
+    if (colfmt == COL_REL16)
+        k_adj_step<COL_REL16><<<std::max(ntiles, 1), 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else if (colfmt == COL_GLOBAL32)
+        k_adj_step<COL_GLOBAL32><<<std::max(ntiles, 1), 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else
+        fail(JAC_E_INVALID, "adjoint step needs global or row-relative columns");
+    JAC_HIP(hipGetLastError());
+}
+
+void launch_adj_grad(int colfmt, int ntiles, hipStream_t st, const SysDev* sysA, const double* X, const double* M,
+                     int32_t L, double* G)
+{
+    if (colfmt == COL_REL16)
+        k_adj_grad<COL_REL16><<<std::max(ntiles, 1), 256, 0, st>>>(sysA, X, M, L, G);
+    else if (colfmt == COL_GLOBAL32)
+        k_adj_grad<COL_GLOBAL32><<<std::max(ntiles, 1), 256, 0, st>>>(sysA, X, M, L, G);
+    else
+        fail(JAC_E_INVALID, "adjoint gradient needs global or row-relative columns");
+    JAC_HIP(hipGetLastError());
+}
+
+void launch_fill_mapped(const double* src, const int32_t* map, int64_t m, double* dst, hipStream_t st)
+{
+    if (m > 0) k_fill_mapped<<<grid1d(m), 256, 0, st>>>(src, map, m, dst);
+    JAC_HIP(hipGetLastError());
+}
+
+}  // namespace jac

@@ -27,6 +27,14 @@ void launch_part_norm(int nrhs, hipStream_t st, const SysDev* sys, int norm_inf,
 void launch_add_correction(double* x, const float* d0, const float* d1, const float* d2, int32_t n, int32_t nrhs,
                            uint32_t which, uint32_t active, hipStream_t st);
 
+// adjoint
+void launch_adj_init(const double* invd, const double* lam, int32_t n, double* mu, double* gb, hipStream_t st);
+void launch_adj_step(int colfmt, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
+                     const double* mu, double* lam_out, double* mu_out, double* gb, const double* invd);
+void launch_adj_grad(int colfmt, int ntiles, hipStream_t st, const SysDev* sysA, const double* X, const double* M,
+                     int32_t L, double* G);
+void launch_fill_mapped(const double* src, const int32_t* map, int64_t m, double* dst, hipStream_t st);
+
 void launch_scatter_vals(const double* vals, const int32_t* slot_of, int64_t nnz, double* out, hipStream_t st);
 void launch_invd(const double* val, const int32_t* diag_slot, int32_t n, double* invd, float* invd32, int32_t* bad,
                  hipStream_t st);

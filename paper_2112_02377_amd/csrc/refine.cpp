@@ -44,6 +44,7 @@ jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t*
     DevMem d_s64;
     d_s64.alloc(sizeof(SysDev));
     JAC_HIP(hipMemcpyAsync(d_s64.p, &s64, sizeof(SysDev), hipMemcpyHostToDevice, h.stream));
+    h.sync();   // s64 is a temporary
 
     double scale[4], thr[4], big[4], prev[4], rel[4];
     int32_t inner_total[4] = {0, 0, 0, 0};

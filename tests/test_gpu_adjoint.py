@@ -1,0 +1,136 @@
+"""GPU: the checkpointed adjoint (jac_adjoint) and the autograd Function,
+against the oracle's full-storage reverse sweep, the dot-product identity and
+central finite differences."""
+import numpy as np
+import pytest
+
+from gpu_util import B, get_x, make, need_gpu, rel_inf, torch
+from oracle import ref
+from paper_2112_02377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def run_adjoint(h, K, c, g, n, nnz):
+    b = B()
+    gb = torch.empty(n, dtype=torch.float64, device="cuda")
+    gv = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    b.jac_adjoint(h, K, c, dev(g), gb, gv)
+    torch.cuda.synchronize()
+    return gb.cpu().numpy(), gv.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode,P,sub,K,c", [(1, 1, None, 60, 7), (1, 3, None, 45, 45), (2, 4, None, 33, 10),
+                                            (3, 4, (2, 2, 1), 50, 8), (1, 2, None, 1, 5)])
+def test_adjoint_matches_full_storage_oracle(mode, P, sub, K, c):
+    need_gpu()
+    b = B()
+    s = W.diffusion_adjoint(10)
+    t = s.extra["x_target"]
+    h = make(s, mode, P, sub)
+    st, xo, _ = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    g = xo - t
+    gb, gv = run_adjoint(h, K, c, g, s.n, s.nnz)
+    sto, gbo, gvo, xk = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K, g)
+    assert np.abs(gb - gbo).max() <= 1e-10 * np.abs(gbo).max()
+    assert np.abs(gv - gvo).max() <= 1e-10 * np.abs(gvo).max()
+    # the handle keeps x_K
+    assert rel_inf(get_x(h, s.n)[0], xk) <= 1e-12
+    b.jac_destroy(h)
+
+
+def test_adjoint_of_nonsymmetric_paper_example():
+    need_gpu()
+    from test_oracle_pins import fig_csr
+    b = B()
+    IA, JA, AA, dense = fig_csr()
+    rng = np.random.default_rng(21)
+    rhs = rng.uniform(-1, 1, 5)
+    g = rng.uniform(-1, 1, 5)
+    h = b.jac_create(5, IA, JA, AA, 1, rhs)
+    for K, c in ((9, 4), (12, 12), (7, 1)):
+        gb, gv = run_adjoint(h, K, c, g, 5, len(AA))
+        sto, gbo, gvo, _ = ref.adjoint(IA, JA, AA, rhs, K, g)
+        assert np.abs(gb - gbo).max() <= 1e-12 * np.abs(gbo).max()
+        assert np.abs(gv - gvo).max() <= 1e-12 * np.abs(gvo).max()
+    b.jac_destroy(h)
+
+
+def test_dot_product_identity_on_device():
+    # <S_K v, w> = <v, S_K^T w>, both sides computed by the library
+    need_gpu()
+    b = B()
+    s = W.diffusion_adjoint(12)
+    rng = np.random.default_rng(8)
+    v = rng.uniform(-1, 1, s.n)
+    w = rng.uniform(-1, 1, s.n)
+    K = 80
+    h = make(s, 2, 3)
+    b.jac_set_rhs(h, dev(v))
+    b.jac_set_x(h, None)
+    b.jac_sweep(h, K)
+    Sv = get_x(h, s.n)[0]
+    STw, _ = run_adjoint(h, K, 16, w, s.n, s.nnz)
+    lhs, rhs = Sv @ w, v @ STw
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+    b.jac_destroy(h)
+
+
+def test_autograd_theta_gradient_matches_oracle_chain_rule():
+    need_gpu()
+    from paper_2112_02377_amd.autograd import JacobiK, diffusion_values
+    s = W.diffusion_adjoint(8)
+    t = dev(s.extra["x_target"])
+    K, c = 70, 9
+    h = make(s, 1, 2)
+    theta = dev(s.extra["theta"]).requires_grad_(True)
+    vals = diffusion_values(theta, s.grid, s.row_ptr, s.extra["slot"])
+    assert np.array_equal(vals.detach().cpu().numpy(), s.vals)     # same assembly as the generator
+    x = JacobiK.apply(vals, dev(s.b[0]), h, K, c)
+    loss = 0.5 * ((x - t) ** 2).sum()
+    loss.backward()
+    gth = theta.grad.cpu().numpy()
+    st, xo, _ = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    _, gbo, gvo, _ = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K, xo - s.extra["x_target"])
+    gth_o = ref.theta_grad(s.extra["theta"], s.grid, s.row_ptr, s.extra["slot"], gvo)
+    assert np.abs(gth - gth_o).max() <= 1e-10 * np.abs(gth_o).max()
+    B().jac_destroy(h)
+
+
+def test_full_size_theta_gradient_against_central_differences():
+    """64^3 conductivities, K = 400 sweeps, checkpoint every 20: dL/dtheta from
+    the autograd Function at 32 seeded entries against central differences
+    (step 1e-6) of the same forward."""
+    need_gpu()
+    from paper_2112_02377_amd.autograd import JacobiK, diffusion_values
+    b = B()
+    s = W.diffusion_adjoint(64)
+    K, c, hstep = 400, 20, 1e-6
+    tnp = s.extra["x_target"]
+    t = dev(tnp)
+    h = make(s, 1, 1)
+    theta = dev(s.extra["theta"]).requires_grad_(True)
+    vals = diffusion_values(theta, s.grid, s.row_ptr, s.extra["slot"])
+    x = JacobiK.apply(vals, dev(s.b[0]), h, K, c)
+    (0.5 * ((x - t) ** 2).sum()).backward()
+    g = theta.grad.cpu().numpy()
+    fd = []
+    for m in s.extra["probes"]:
+        xs = []
+        for sign in (1, -1):
+            th = s.extra["theta"].copy()
+            th[m] += sign * hstep
+            v = W.diffusion_values(th, 64, 64, 64, s.row_ptr, s.extra["slot"])
+            b.jac_set_values(h, dev(v))
+            b.jac_set_x(h, None)
+            b.jac_sweep(h, K)
+            xs.append(get_x(h, s.n)[0])
+        fd.append(np.sum((xs[0] - xs[1]) * (xs[0] + xs[1] - 2 * tnp)) / (4 * hstep))
+    fd = np.array(fd)
+    gp = g[s.extra["probes"]]
+    assert np.all(np.abs(gp - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())), (gp, fd)
+    b.jac_destroy(h)
