@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the FP32-refinement, batched and adjoint comparisons")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -57,8 +59,10 @@ def src_digest():
 
 
 def traffic_from_profile(kernel_tag, launches_bytes):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, when it was taken on the current kernel sources; else None."""
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE
+    counters scaled by a copy-kernel calibration) from the committed counter
+    summary profiles/traffic.json, when it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -83,6 +87,104 @@ def cpu_baseline(sysm, sweeps):
             "sample": f"{sweeps} sweeps of the same {round(sysm.n ** (1 / 3))}^3 system (residual norm per sweep), "
                       f"plain C FP64 oracle, {threads} OpenMP threads, {dt:.2f} s",
             "sweeps_per_s": round(sweeps / dt, 3)}
+
+
+def _timed(torch, stream, fn):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    r = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), r
+
+
+def secondary(B, W, torch, stream, with_oracle=True):
+    """The comparisons the metric names, each against the plain FP64 sweep on
+    the same GPU: FP32 inner sweeps with FP64 refinement (96^3 27-point
+    FE-like matrix, to 1e-10), the batched persistent solve (256 diffusion
+    systems x 4 right-hand sides, to 1e-8) against 256 separate solves, and
+    the adjoint (64^3 diffusion, K = 400, checkpoint every 20) against its
+    forward sweeps.  Times are HIP-event times on the handles' stream."""
+    out = {}
+    sc = stream.cuda_stream
+    # -- FP32 refinement
+    s = W.fe27(96, workload=3)
+    h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+    B.jac_partition(h, B.JAC_BANDROW, 64)
+    info = B.jac_get_info(h)
+    res = {}
+    for prec, name in ((B.JAC_FP64, "fp64"), (B.JAC_FP32_REFINE, "fp32_refine")):
+        B.jac_set_x(h, None)
+        B.jac_solve(h, 1e-10, 100000, B.JAC_NORM_L2_REL, prec)      # warm
+        B.jac_set_x(h, None)
+        ms, (st, sw, rr) = _timed(torch, stream, lambda: B.jac_solve(h, 1e-10, 100000, B.JAC_NORM_L2_REL, prec))
+        x = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        B.jac_get_x(h, x)
+        torch.cuda.synchronize()
+        res[name] = dict(ms=round(ms, 3), sweeps=int(sw[0]), relres=float(rr[0]), x=x.cpu().numpy())
+    bytes64 = info["alg_bytes_per_sweep"]
+    bytes32 = 8 * info["nnz"] + 4 * (s.n + 1) + 16 * s.n
+    ref_err = None
+    if with_oracle:
+        from oracle import ref
+        st, xo, ko, rro = ref.refine_reference(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-10,
+                                               threads=min(16, os.cpu_count() or 1))
+        scale = float(abs(xo).max())
+        ref_err = {k: float(abs(v["x"] - xo).max() / scale) for k, v in res.items()}
+        ref_err["oracle_sweeps"] = int(ko)
+    out["fp32_refine"] = {
+        "workload": f"fe27 96^3 (n={s.n}, nnz={s.nnz}), 1.05-dominant, tol 1e-10, 64 bands",
+        "fp64_ms": res["fp64"]["ms"], "fp64_sweeps": res["fp64"]["sweeps"], "fp64_relres": res["fp64"]["relres"],
+        "refine_ms": res["fp32_refine"]["ms"], "refine_inner_sweeps": res["fp32_refine"]["sweeps"],
+        "refine_relres": res["fp32_refine"]["relres"],
+        "speedup_vs_fp64": round(res["fp64"]["ms"] / res["fp32_refine"]["ms"], 3),
+        "fp64_GBps": round(res["fp64"]["sweeps"] * bytes64 / res["fp64"]["ms"] / 1e6, 1),
+        "inner_GBps_fp32_model": round(res["fp32_refine"]["sweeps"] * bytes32 / res["fp32_refine"]["ms"] / 1e6, 1),
+        "max_rel_err_vs_fp64_oracle": ref_err}
+    B.jac_destroy(h)
+    # -- batched
+    systems = W.diffusion_batch(256, workload=4)
+    hs = [B.jac_create(x.n, x.row_ptr, x.col_idx, x.vals, 4, x.b.reshape(-1), stream=sc) for x in systems]
+    ms_b, (st, swb, rrb) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
+    for hh in hs:
+        B.jac_set_x(hh, None)
+
+    def seq():
+        return [B.jac_solve(hh, 1e-8, 1000000) for hh in hs]
+    ms_s, rs = _timed(torch, stream, seq)
+    same = all(int((swb[i, :4] != r[1]).sum()) == 0 for i, r in enumerate(rs))
+    alg = 0
+    for x, k in zip(systems, swb):
+        alg += (12 * x.nnz + 4 * (x.n + 1) + 8 * x.n + 96 * x.n) * (int(k[:4].max()) + 1)
+    out["batched"] = {
+        "workload": f"256 diffusion systems, edges U[16,64], n total {sum(x.n for x in systems)}, 4 rhs, tol 1e-8",
+        "persistent_ms": round(ms_b, 3), "sequential_ms": round(ms_s, 3),
+        "speedup_vs_sequential": round(ms_s / ms_b, 3), "max_sweeps": int(swb[:, :4].max()),
+        "sum_system_sweeps": int(swb[:, :4].max(axis=1).sum()),
+        "persistent_alg_GBps": round(alg / ms_b / 1e6, 1), "sequential_alg_GBps": round(alg / ms_s / 1e6, 1),
+        "sweep_counts_equal": bool(same)}
+    for hh in hs:
+        B.jac_destroy(hh)
+    # -- adjoint
+    s = W.diffusion_adjoint(64, workload=5)
+    h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+    gx = torch.from_numpy(s.extra["x_target"]).cuda()
+    gb = torch.empty_like(gx)
+    gv = torch.empty(s.nnz, dtype=torch.float64, device="cuda")
+    B.jac_set_x(h, None)
+    B.jac_sweep(h, 400)
+    B.jac_set_x(h, None)
+    ms_f, _ = _timed(torch, stream, lambda: B.jac_sweep(h, 400))
+    B.jac_adjoint(h, 400, 20, gx, gb, gv)
+    ms_a, _ = _timed(torch, stream, lambda: B.jac_adjoint(h, 400, 20, gx, gb, gv))
+    fb = B.jac_get_info(h)["alg_bytes_per_sweep"]
+    out["adjoint"] = {"workload": "diffusion 64^3, K = 400 sweeps, checkpoint every 20", "forward_ms": round(ms_f, 3),
+                      "adjoint_ms": round(ms_a, 3), "adjoint_over_forward": round(ms_a / ms_f, 3),
+                      "forward_GBps": round(400 * fb / ms_f / 1e6, 1)}
+    B.jac_destroy(h)
+    return out
 
 
 def main():
@@ -157,6 +259,8 @@ def main():
     alg = {m: infos[m]["alg_bytes_per_sweep"] for m in sel}
     total_bytes = args.steps * K * sum(alg.values())
     value = total_bytes / (ms_total / 1e3) / 1e9
+    for m in sel:
+        infos[m] = B.jac_get_info(handles[m])
     per_mode = {}
     for m in sel:
         avg = sum(loop_ms[m]) / len(loop_ms[m])
@@ -173,17 +277,19 @@ def main():
     kern = {}
     for m in sel:
         kname = "k_loop" if args.loop else "k_sweep"
-        tag = f"{kname}<double,1,staged>" if infos[m]["col_bytes"] == 2 else f"{kname}<double,1,global>"
+        cm = 2 if m in ("JBO", "JSS") else (1 if infos[m]["col_bytes"] == 2 else 0)
+        tag = f"{kname}<double, 1, {cm}>"
         kern.setdefault(tag, []).append(m)
     dom = max(kern, key=lambda t: sum(per_mode[m]["loop_ms"] for m in kern[t]))
     dm = kern[dom]
-    avg_launch_ms = sum(per_mode[m]["loop_ms"] for m in dm) / len(dm)
-    bytes_launch = sum(alg[m] for m in dm) / len(dm) * K
+    # one launch of the sweep kernel is one sweep
+    avg_launch_ms = sum(per_mode[m]["loop_ms"] for m in dm) / len(dm) / K
+    bytes_launch = sum(alg[m] for m in dm) / len(dm)
     achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, bytes_launch),
             "kernel": dom, "modes": dm, "alg_bytes_per_launch": int(bytes_launch),
-            "avg_launch_ms": round(avg_launch_ms, 3)}
+            "avg_launch_ms": round(avg_launch_ms, 5)}
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -191,10 +297,12 @@ def main():
                                   f"(JSS: 8x8x8 subdomains)", "n": s.n, "nnz": s.nnz, "sweeps": K,
                       "parallelism": "1 GPU", "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
            "roofline": roof, "modes": per_mode, "wall_s": round(wall, 3)}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sweeps)
     for h in handles.values():
         B.jac_destroy(h)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sweeps)
+    if not args.no_secondary:
+        out["secondary"] = secondary(B, W, torch, stream, with_oracle=not args.no_cpu)
     print(json.dumps(out), flush=True)
 
 

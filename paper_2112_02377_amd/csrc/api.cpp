@@ -109,6 +109,10 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     sync();
     part = std::move(np);
     plan = std::move(pl);
+    part_mode = mode;
+    part_nparts = nparts;
+    part_has_sub = sub_grid != nullptr;
+    for (int q = 0; q < 3; ++q) part_sub[q] = sub_grid ? sub_grid[q] : 0;
     have_t = false;                 // the transposed layout follows the split
     upload(d.tile_row0, plan.tile_row0, stream);
     upload(d.tile_slice0, plan.tile_slice0, stream);

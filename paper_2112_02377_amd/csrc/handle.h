@@ -66,6 +66,11 @@ struct Handle {
     Options opt;
     DeviceArrays d;
     double bnorm[4] = {0, 0, 0, 0};
+    // arguments of the current split (the autotuner re-plans with them)
+    int part_mode = JAC_BANDROW;
+    int32_t part_nparts = 1;
+    int32_t part_sub[3] = {0, 0, 0};
+    bool part_has_sub = false;
     int last_grid = 0;
     int last_status = 0;
     double last_loop_ms = 0.0;

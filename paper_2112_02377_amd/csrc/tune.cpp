@@ -1,0 +1,136 @@
+// Autotuner: times candidate tile shapes (rows per tile) and workgroup sizes
+// for the fused sweep on the handle's own matrix and split, keeps the fastest,
+// and caches the choice in a text file named by $JAC_TUNE_CACHE, one line per
+// key "n nnz nrhs mode nparts sx sy sz fp32" -> "tile_rows block us_per_sweep".
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "handle.h"
+#include "launch.h"
+
+namespace jac {
+namespace {
+
+std::mutex g_cache_mutex;
+
+struct Cand {
+    int32_t tile_rows, block;
+};
+const Cand kCands[] = {{256, 256}, {512, 256}, {1024, 256}, {2048, 256}, {512, 128},
+                       {512, 512}, {1024, 512}, {2048, 512}, {4096, 512}};
+
+std::string cache_key(const Handle& h)
+{
+    std::ostringstream k;
+    k << h.a.n << ' ' << h.a.nnz() << ' ' << h.nrhs << ' ' << h.part_mode << ' ' << h.part_nparts << ' '
+      << h.part_sub[0] << ' ' << h.part_sub[1] << ' ' << h.part_sub[2] << " 0";
+    return k.str();
+}
+
+bool cache_lookup(const std::string& key, int32_t& rows, int32_t& block)
+{
+    const char* path = std::getenv("JAC_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        std::istringstream v(line.substr(bar + 1));
+        double us = 0;
+        if (v >> rows >> block >> us) found = true;     // the last entry for a key wins
+    }
+    return found;
+}
+
+void cache_store(const std::string& key, int32_t rows, int32_t block, double us)
+{
+    const char* path = std::getenv("JAC_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    std::ofstream f(path, std::ios::app);
+    f << key << '|' << rows << ' ' << block << ' ' << us << '\n';
+}
+
+// Average duration of `sweeps` fixed sweeps (after two unrecorded ones), ms.
+double time_sweeps(Handle& h, int32_t sweeps)
+{
+    std::vector<SysDev> sys = {h.sysdev(false)};
+    std::vector<int32_t> tb = {0, h.plan.ntiles};
+    const int32_t timing = h.opt.timing;
+    h.opt.timing = 0;
+    run_loop(h, sys, false, false, 2, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, h.lds_fp_bytes(false),
+             h.lds_runs(), h.plan.colfmt, h.nrhs);
+    h.opt.timing = 1;
+    run_loop(h, sys, false, false, sweeps, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb,
+             h.lds_fp_bytes(false), h.lds_runs(), h.plan.colfmt, h.nrhs);
+    h.opt.timing = timing;
+    return h.last_loop_ms;
+}
+
+}  // namespace
+}  // namespace jac
+
+using namespace jac;
+
+extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
+{
+    try {
+        if (!hp) fail(JAC_E_INVALID, "NULL handle");
+        if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
+        Handle& h = *hp;
+        const std::string key = cache_key(h);
+        const int32_t* sub = h.part_has_sub ? h.part_sub : nullptr;
+        int32_t rows = 0, block = 0;
+        if (cache_lookup(key, rows, block)) {
+            h.opt.block = block;
+            if (rows != h.opt.tile_rows) {
+                h.opt.tile_rows = rows;
+                h.replan(h.part_mode, h.part_nparts, sub);
+            }
+            return JAC_OK;
+        }
+        // keep the caller's iterate across the trials
+        DevMem xs;
+        xs.alloc((size_t)h.a.n * h.nrhs * sizeof(double));
+        h.get_x_dev(static_cast<double*>(xs.p));
+        double best = 1e300;
+        Cand pick = {h.opt.tile_rows, h.opt.block};
+        for (const Cand& c : kCands) {
+            if (c.tile_rows != h.opt.tile_rows) {
+                h.opt.tile_rows = c.tile_rows;
+                h.replan(h.part_mode, h.part_nparts, sub);
+            }
+            h.opt.block = c.block;
+            const double ms = time_sweeps(h, sweeps_per_trial);
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        h.opt.block = pick.block;
+        if (pick.tile_rows != h.opt.tile_rows) {
+            h.opt.tile_rows = pick.tile_rows;
+            h.replan(h.part_mode, h.part_nparts, sub);
+        }
+        launch_gather_in(static_cast<const double*>(xs.p), static_cast<const int32_t*>(h.d.perm.p), h.a.n, h.nrhs,
+                         static_cast<double*>(h.d.x0.p), h.stream);
+        h.sync();
+        cache_store(key, pick.tile_rows, pick.block, best * 1e3 / sweeps_per_trial);
+        return JAC_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return JAC_E_NOMEM;
+    }
+}
