@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--lds-elems", type=int, default=0)
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the FP32-refinement, batched and adjoint comparisons")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -225,6 +226,8 @@ def main():
             B.jac_set_option(h, B.JAC_OPT_BLOCK, args.block)
         if args.wg_per_cu:
             B.jac_set_option(h, B.JAC_OPT_WG_PER_CU, args.wg_per_cu)
+        if args.lds_elems:
+            B.jac_set_option(h, B.JAC_OPT_LDS_ELEMS, args.lds_elems)
         B.jac_set_grid(h, N, N, N)
         B.jac_partition(h, mode, P, sub)
         B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
