@@ -175,35 +175,41 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             lds_ro[t] = run_lds[run0 + t];
         }
         __syncthreads();
+        // element e of the footprint lies in the last run starting at or
+        // before it: a binary search whose steps depend on nr only, so every
+        // lane takes the same ones and the SU searches of a batch interleave.
+        // A probe past the last run reads the last run instead, which can
+        // only move lo to the last run when that is the answer.  Lanes past
+        // the end of the footprint redo its last element: they load and store
+        // the same value to the same place as its own lane, so no load or
+        // store needs a predicate and the batch's loads issue together.
+        const int32_t top = nr > 1 ? (int32_t)(0x80000000u >> __builtin_clz((uint32_t)(nr - 1))) : 0;
         for (int32_t e0 = threadIdx.x; e0 < fp; e0 += blockDim.x * SU) {
-            int32_t g[SU];
+            int32_t e[SU], lo[SU];
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
-                const int32_t e = e0 + u * (int32_t)blockDim.x;
-                g[u] = -1;
-                if (e < fp) {
-                    int32_t lo = 0, hi = nr - 1;              // last run starting at or before e
-                    while (lo < hi) {
-                        const int32_t mid = (lo + hi + 1) >> 1;
-                        if (lds_ro[mid] <= e) lo = mid; else hi = mid - 1;
-                    }
-                    g[u] = lds_rs[lo] + (e - lds_ro[lo]);
+                e[u] = min(e0 + u * (int32_t)blockDim.x, fp - 1);
+                lo[u] = 0;
+            }
+            for (int32_t step = top; step > 0; step >>= 1) {
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int32_t t = min(lo[u] + step, nr - 1);
+                    lo[u] = lds_ro[t] <= e[u] ? t : lo[u];
                 }
             }
             T v[SU][NRHS];
 #pragma unroll
-            for (int u = 0; u < SU; ++u)
-                if (g[u] >= 0) {
+            for (int u = 0; u < SU; ++u) {
+                const int64_t g = (int64_t)(lds_rs[lo[u]] + (e[u] - lds_ro[lo[u]]));
 #pragma unroll
-                    for (int c = 0; c < NRHS; ++c) v[u][c] = x[(int64_t)g[u] * NRHS + c];
-                }
+                for (int c = 0; c < NRHS; ++c) v[u][c] = x[g * NRHS + c];
+            }
 #pragma unroll
-            for (int u = 0; u < SU; ++u)
-                if (g[u] >= 0) {
-                    const int32_t e = e0 + u * (int32_t)blockDim.x;
+            for (int u = 0; u < SU; ++u) {
 #pragma unroll
-                    for (int c = 0; c < NRHS; ++c) lds_x[e * NRHS + c] = v[u][c];
-                }
+                for (int c = 0; c < NRHS; ++c) lds_x[e[u] * NRHS + c] = v[u][c];
+            }
         }
         __syncthreads();
     }
