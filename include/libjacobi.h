@@ -193,7 +193,10 @@ jac_status jac_solve_batched(const jac_handle *hs, int32_t nsys, double tol, int
  * given gx_dev = dL/dx_K (n, original order), writes gb_dev = dL/db (n) and
  * gvals_dev = dL/dvals (nnz, caller's CSR entry order, diagonal included).
  * Iterates are checkpointed every ckpt_every sweeps and recomputed per
- * segment.  Leaves x = x_K in the handle.  Either output may be NULL. */
+ * segment.  Leaves x = x_K in the handle.  Either output may be NULL.
+ * Device memory: ceil(K/ckpt_every) + 2*ckpt_every + 5 vectors of n doubles plus
+ * one double per stored slot (at most JAC_OPT_CKPT_MEM_MB, else
+ * JAC_E_INVALID), kept by the handle for later calls until jac_destroy. */
 jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double *gx_dev, double *gb_dev,
                        double *gvals_dev);
 

@@ -8,9 +8,12 @@
 //   dL/da_ij -= mu_{k+1,i} x_{k,j}      (j != i)
 //   dL/da_ii -= mu_{k+1,i} x_{k+1,i}    (through both A x_k and 1/a_ii)
 // The iterates are kept only every ckpt_every sweeps.  Each segment is swept
-// again from its checkpoint with the same kernel (bit-identical iterates),
-// then reversed step by step on A^T, and its dL/dvals contributions are added
-// in one pass over A's stored entries.
+// again from its checkpoint with the same kernel (bit-identical iterates; its
+// last iterate is the next checkpoint and is copied, not recomputed), then
+// reversed step by step on A^T, and its dL/dvals contributions are added in
+// one pass over A's stored entries.  The forward and the reverse queue all
+// their launches without waiting for the device; the working buffers stay
+// with the handle for the next call.
 #include <algorithm>
 #include <cstring>
 
@@ -86,18 +89,6 @@ static void build_transpose(Handle& h)
     h.have_t = true;
 }
 
-static void sweep_fixed(Handle& h, int32_t K)
-{
-    if (K <= 0) return;
-    std::vector<SysDev> sys = {h.sysdev(false)};
-    std::vector<int32_t> tb = {0, h.plan.ntiles};
-    run_loop(h, sys, false, false, K, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, h.lds_fp_bytes(false),
-             h.lds_runs(), h.plan.colfmt, h.nrhs);
-    uint32_t which = 0;
-    for (int c = 0; c < h.nrhs; ++c) which |= (uint32_t)(K % 3) << (2 * c);
-    h.settle(which);
-}
-
 }  // namespace jac
 
 using namespace jac;
@@ -120,10 +111,14 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         if (need > (size_t)h.opt.ckpt_mb << 20)
             fail(JAC_E_INVALID, "adjoint buffers exceed JAC_OPT_CKPT_MEM_MB; raise it or the checkpoint stride");
         if (!h.have_t) build_transpose(h);
+        DeviceArrays& d = h.d;
         // A^T values from A's slots (coefficients may have changed since)
-        launch_fill_mapped(static_cast<const double*>(h.d.val.p), static_cast<const int32_t*>(h.td.t_map.p),
+        launch_fill_mapped(static_cast<const double*>(d.val.p), static_cast<const int32_t*>(h.td.t_map.p),
                            h.tplan.slots, static_cast<double*>(h.td.val.p), st);
-        SysDev sT{};
+        // device descriptors: [0] A^T, [1] A with global columns (gradient pass)
+        SysDev desc[2];
+        SysDev& sT = desc[0];
+        sT = SysDev{};
         sT.tile_row0 = static_cast<const int32_t*>(h.td.tile_row0.p);
         sT.tile_slice0 = static_cast<const int32_t*>(h.td.tile_slice0.p);
         sT.slice_off = static_cast<const int64_t*>(h.td.slice_off.p);
@@ -134,78 +129,88 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         sT.ntiles = h.tplan.ntiles;
         sT.nrhs = 1;
         sT.colfmt = h.tplan.colfmt;
-        DevMem d_sT, d_sA;
-        d_sT.alloc(sizeof(SysDev));
-        JAC_HIP(hipMemcpyAsync(d_sT.p, &sT, sizeof(SysDev), hipMemcpyHostToDevice, st));
-        SysDev sA = h.sysdev(false);
-        SysDev sG = sA;                       // A's layout with global columns, for the gradient
+        const SysDev sA = h.sysdev(false);
+        desc[1] = sA;
         int gfmt = h.plan.colfmt;
         if (gfmt == COL_LOCAL16) {
-            sG.col32 = static_cast<const int32_t*>(h.td.a_gcol.p);
+            desc[1].col32 = static_cast<const int32_t*>(h.td.a_gcol.p);
             gfmt = COL_GLOBAL32;
         }
-        DevMem d_sG;
-        d_sG.alloc(sizeof(SysDev));
-        JAC_HIP(hipMemcpyAsync(d_sG.p, &sG, sizeof(SysDev), hipMemcpyHostToDevice, st));
-        d_sA.alloc(sizeof(SysDev));
-        JAC_HIP(hipMemcpyAsync(d_sA.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
-        JAC_HIP(hipStreamSynchronize(st));   // host structs are temporaries
+        // recompute sweeps: sweep m of a segment reads X[m] and writes X[m+1]
+        d.adj_X.ensure((size_t)(c + 1) * vec);
+        auto Xm = [&](int m) { return static_cast<double*>(d.adj_X.p) + (size_t)m * n; };
+        std::vector<SysDev> segs((size_t)c, sA);
+        for (int32_t m = 0; m < c; ++m) {
+            segs[m].x[0] = Xm(m);
+            segs[m].x[1] = Xm(m + 1);
+            segs[m].x[2] = Xm(m + 1);
+        }
+        d.adj_sys.ensure(sizeof(desc));
+        d.adj_segs.ensure(sizeof(SysDev) * (size_t)c);
+        JAC_HIP(hipMemcpyAsync(d.adj_sys.p, desc, sizeof(desc), hipMemcpyHostToDevice, st));
+        JAC_HIP(hipMemcpyAsync(d.adj_segs.p, segs.data(), sizeof(SysDev) * (size_t)c, hipMemcpyHostToDevice, st));
+        d.sys.ensure(sizeof(SysDev));
+        JAC_HIP(hipMemcpyAsync(d.sys.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
+        d.state.ensure(sizeof(SysState));
+        JAC_HIP(hipStreamSynchronize(st));   // the host descriptors are temporaries
+        const SysDev* d_sT = static_cast<const SysDev*>(d.adj_sys.p);
+        const SysDev* d_sG = d_sT + 1;
+        d.adj_ck.ensure(std::max<size_t>((size_t)nseg * vec, 16));
+        d.adj_M.ensure((size_t)c * vec);
+        d.adj_lam0.ensure(vec);
+        d.adj_lam1.ensure(vec);
+        d.adj_carry.ensure(vec);
+        d.adj_gb.ensure(vec);
+        d.adj_G.ensure((size_t)h.plan.slots * 8);
+        JAC_HIP(hipMemsetAsync(d.adj_G.p, 0, (size_t)h.plan.slots * 8, st));
+        JAC_HIP(hipMemsetAsync(d.adj_gb.p, 0, vec, st));
+        auto Mm = [&](int m) { return static_cast<double*>(d.adj_M.p) + (size_t)m * n; };
+        auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
+        double* xb[3] = {static_cast<double*>(d.x0.p), static_cast<double*>(d.x1.p), static_cast<double*>(d.x2.p)};
 
-        DevMem ck, X, M, lam0, lam1, carry, gb, G;
-        ck.alloc(std::max<size_t>((size_t)nseg * vec, 16));
-        X.alloc((size_t)(c + 1) * vec);
-        M.alloc((size_t)c * vec);
-        lam0.alloc(vec);
-        lam1.alloc(vec);
-        carry.alloc(vec);
-        gb.alloc(vec);
-        G.alloc((size_t)h.plan.slots * 8);
-        JAC_HIP(hipMemsetAsync(G.p, 0, (size_t)h.plan.slots * 8, st));
-        JAC_HIP(hipMemsetAsync(gb.p, 0, vec, st));
-        auto Xm = [&](int m) { return static_cast<double*>(X.p) + (size_t)m * n; };
-        auto Mm = [&](int m) { return static_cast<double*>(M.p) + (size_t)m * n; };
-        auto CK = [&](int j) { return static_cast<double*>(ck.p) + (size_t)j * n; };
-
-        // forward with checkpoints, from x_0 = 0
-        launch_gather_in(nullptr, static_cast<const int32_t*>(h.d.perm.p), n, 1, static_cast<double*>(h.d.x0.p), st);
-        for (int32_t j = 0; j < nseg; ++j) {
-            JAC_HIP(hipMemcpyAsync(CK(j), h.d.x0.p, vec, hipMemcpyDeviceToDevice, st));
-            sweep_fixed(h, std::min(c, K - j * c));
+        // forward from x_0 = 0, one launch per sweep on the handle's three
+        // iterate buffers (x_k in buffer k mod 3); x_{jc} kept as checkpoint j
+        void* fn = sweep_kernel(false, 1, h.plan.colfmt, false);
+        const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
+        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const int grid = std::max(h.plan.ntiles, 1) + 1;
+        launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, xb[0], st);
+        launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
+        {
+            LoopParams p{};
+            p.sys = static_cast<const SysDev*>(d.sys.p);
+            p.st = static_cast<SysState*>(d.state.p);
+            p.nsys = 1;
+            p.k0 = 0;
+            p.kend = K;
+            p.solve = 0;
+            for (int32_t k = 0; k < K; ++k) {
+                if (k % c == 0) JAC_HIP(hipMemcpyAsync(CK(k / c), xb[k % 3], vec, hipMemcpyDeviceToDevice, st));
+                launch_sweep1(fn, grid, h.opt.block, lds, st, p, k, fpb, runs);
+            }
         }
         if (K > 0) {
             // lambda_K (internal order), mu_K = D^{-1} lambda_K, gb = mu_K
-            launch_gather_in(gx_dev, static_cast<const int32_t*>(h.d.perm.p), n, 1, static_cast<double*>(lam0.p),
-                             st);
+            double* lin = static_cast<double*>(d.adj_lam0.p);
+            double* lout = static_cast<double*>(d.adj_lam1.p);
+            launch_gather_in(gx_dev, static_cast<const int32_t*>(d.perm.p), n, 1, lin, st);
             const int32_t Llast = K - (nseg - 1) * c;
-            launch_adj_init(static_cast<const double*>(h.d.invd.p), static_cast<const double*>(lam0.p), n,
-                            Mm(Llast - 1), static_cast<double*>(gb.p), st);
-            // one-sweep kernels that read X[m] and write X[m+1]
-            std::vector<SysDev> segs((size_t)c);
-            DevMem d_segs;
-            d_segs.alloc(sizeof(SysDev) * (size_t)c);
-            void* fn = sweep_kernel(false, 1, h.plan.colfmt, false);
-            const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
-            const size_t lds = loop_lds_bytes(fpb, runs, 0);
-            const int grid = std::max(h.plan.ntiles, 1) + 1;
-            launch_init_state(static_cast<SysState*>(h.d.state.p), 1, st);
-            double* lin = static_cast<double*>(lam0.p);
-            double* lout = static_cast<double*>(lam1.p);
+            launch_adj_init(static_cast<const double*>(d.invd.p), lin, n, Mm(Llast - 1),
+                            static_cast<double*>(d.adj_gb.p), st);
+            // the recompute launches decide nothing (sweep 0 of a fresh state)
+            launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
             for (int32_t j = nseg - 1; j >= 0; --j) {
                 const int32_t k0 = j * c;
                 const int32_t L = std::min(c, K - k0);
+                // x_{k0} .. x_{k0+L}: both ends are known (checkpoints, or x_K
+                // from the forward), the sweeps in between are recomputed
                 JAC_HIP(hipMemcpyAsync(Xm(0), CK(j), vec, hipMemcpyDeviceToDevice, st));
-                for (int32_t m = 0; m < L; ++m) {
-                    segs[m] = sA;
-                    segs[m].x[0] = Xm(m);
-                    segs[m].x[1] = Xm(m + 1);
-                    segs[m].x[2] = Xm(m + 1);
-                }
-                JAC_HIP(hipMemcpyAsync(d_segs.p, segs.data(), sizeof(SysDev) * (size_t)L, hipMemcpyHostToDevice, st));
-                JAC_HIP(hipStreamSynchronize(st));
-                for (int32_t m = 0; m < L; ++m) {
+                JAC_HIP(hipMemcpyAsync(Xm(L), j + 1 < nseg ? CK(j + 1) : xb[K % 3], vec, hipMemcpyDeviceToDevice,
+                                       st));
+                for (int32_t m = 0; m + 1 < L; ++m) {
                     LoopParams p{};
-                    p.sys = static_cast<const SysDev*>(d_segs.p) + m;
-                    p.st = static_cast<SysState*>(h.d.state.p);
+                    p.sys = static_cast<const SysDev*>(d.adj_segs.p) + m;
+                    p.st = static_cast<SysState*>(d.state.p);
                     p.nsys = 1;
                     p.k0 = 0;
                     p.kend = 1;
@@ -215,23 +220,23 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                 for (int32_t m = L - 1; m >= 0; --m) {
                     const int32_t k = k0 + m;
                     double* mu_out = nullptr;
-                    if (k >= 1) mu_out = m >= 1 ? Mm(m - 1) : static_cast<double*>(carry.p);
-                    launch_adj_step(h.tplan.colfmt, h.tplan.ntiles, st, static_cast<const SysDev*>(d_sT.p), lin,
-                                    Mm(m), lout, mu_out, static_cast<double*>(gb.p),
-                                    static_cast<const double*>(h.d.invd.p));
+                    if (k >= 1) mu_out = m >= 1 ? Mm(m - 1) : static_cast<double*>(d.adj_carry.p);
+                    launch_adj_step(h.tplan.colfmt, h.tplan.ntiles, st, d_sT, lin, Mm(m), lout, mu_out,
+                                    static_cast<double*>(d.adj_gb.p), static_cast<const double*>(d.invd.p));
                     std::swap(lin, lout);
                 }
-                launch_adj_grad(gfmt, h.plan.ntiles, st, static_cast<const SysDev*>(d_sG.p), Xm(0), Mm(0), L,
-                                static_cast<double*>(G.p));
-                if (j > 0) JAC_HIP(hipMemcpyAsync(Mm(c - 1), carry.p, vec, hipMemcpyDeviceToDevice, st));
+                launch_adj_grad(gfmt, h.plan.ntiles, st, d_sG, Xm(0), Mm(0), L, static_cast<double*>(d.adj_G.p));
+                if (j > 0) JAC_HIP(hipMemcpyAsync(Mm(c - 1), d.adj_carry.p, vec, hipMemcpyDeviceToDevice, st));
             }
         }
+        // the handle keeps x_K in its first iterate buffer
+        h.settle((uint32_t)(K % 3));
         if (gb_dev)
-            launch_scatter_out(static_cast<const double*>(gb.p), static_cast<const int32_t*>(h.d.perm.p), n, 1, gb_dev,
-                               st);
+            launch_scatter_out(static_cast<const double*>(d.adj_gb.p), static_cast<const int32_t*>(d.perm.p), n, 1,
+                               gb_dev, st);
         if (gvals_dev)
-            launch_fill_mapped(static_cast<const double*>(G.p), static_cast<const int32_t*>(h.d.slot_of_caller.p), nnz,
-                               gvals_dev, st);
+            launch_fill_mapped(static_cast<const double*>(d.adj_G.p), static_cast<const int32_t*>(d.slot_of_caller.p),
+                               nnz, gvals_dev, st);
         h.sync();
         return JAC_OK;
     } catch (const Error& e) {

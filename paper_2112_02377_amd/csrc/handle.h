@@ -23,6 +23,7 @@ struct DevMem {
     ~DevMem();
     void reset();
     void* alloc(size_t nb);
+    void* ensure(size_t nb) { return bytes >= nb && p ? p : alloc(nb); }   // grow-only
 };
 
 struct Options {
@@ -49,8 +50,10 @@ struct DeviceArrays {
     DevMem batch_sys, batch_state, batch_tile_base;
     // FP32 refinement
     DevMem r32, d0, d1, d2, rpart;
-    // adjoint
+    // adjoint: A^T slot map, A's global columns (staged plans), and the
+    // working buffers, kept between calls (grow-only)
     DevMem t_map, a_gcol;
+    DevMem adj_ck, adj_X, adj_M, adj_lam0, adj_lam1, adj_carry, adj_gb, adj_G, adj_sys, adj_segs;
 };
 
 struct Handle {

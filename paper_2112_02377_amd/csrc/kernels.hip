@@ -31,7 +31,7 @@ namespace jac {
 namespace {
 
 constexpr int KB = 8;      // slot batch: loads issued together before use
-constexpr int SU = 4;      // staging batch
+constexpr int SU = 8;      // staging batch
 
 // Pointer into global (device) memory: lets the compiler emit global_* loads.
 template <typename V>
@@ -285,7 +285,8 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             }
         }
     }
-    if constexpr (STAGED) __syncthreads();   // LDS is reused by the next tile
+    // LDS is reused by the next tile: every caller follows with block_reduce,
+    // whose barrier all waves pass only after their last slice
 }
 
 // Reduce the tile partials of sweep k of system s in tile order and take the
@@ -960,7 +961,9 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
 // Gradient of one segment, on A's sliced layout (SDDMM form): for every slot
 // (row i, column j) of A, G -= sum_m mu[m][i] * (j == i ? x[m+1][i] : x[m][j]),
 // m ascending.  mu[m] = mu_{k0+m+1}, x[m] = x_{k0+m}; both node-major
-// [m][n] (m-th vector at offset m*n).
+// [m][n] (m-th vector at offset m*n).  A lane takes KB slots of its row at a
+// time: per m one load of mu[m][i] serves all of them and their KB gathers
+// are independent.
 template <int CM>
 __global__ void __launch_bounds__(512) k_adj_grad(const SysDev* sysA, const double* __restrict__ X,
                                                  const double* __restrict__ M, int32_t L, double* __restrict__ G)
@@ -969,6 +972,8 @@ __global__ void __launch_bounds__(512) k_adj_grad(const SysDev* sysA, const doub
     const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
     const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
     const gptr<const double> Xg = (gptr<const double>)X;
+    const gptr<const double> Mg = (gptr<const double>)M;
+    const gptr<double> Gg = (gptr<double>)G;
     const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
     const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
     const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
@@ -987,18 +992,39 @@ __global__ void __launch_bounds__(512) k_adj_grad(const SysDev* sysA, const doub
             const int32_t w = (int32_t)((slice_off[s + 1] - soff) >> 6);
             const int32_t i = row0 + lane;
             if (i >= r1) continue;
-            for (int32_t kk = 0; kk < w; ++kk) {
-                const int64_t slot = soff + (int64_t)kk * 64 + lane;
-                int32_t j;
-                if constexpr (CM == COL_GLOBAL32) j = col32[slot];
-                else j = i + (int32_t)(int16_t)col16[slot];
-                const bool diag = (j == i);
-                double acc = 0.0;
-                for (int32_t m = 0; m < L; ++m) {
-                    const double xv = diag ? Xg[(int64_t)(m + 1) * n + i] : Xg[(int64_t)m * n + j];
-                    acc = __builtin_fma(M[(int64_t)m * n + i], xv, acc);
+            for (int32_t k0 = 0; k0 < w; k0 += KB) {
+                // x index per slot, relative to x[m]: the diagonal reads x[m+1][i]
+                int64_t jx[KB];
+                double acc[KB];
+#pragma unroll
+                for (int u = 0; u < KB; ++u) {
+                    acc[u] = 0.0;
+                    jx[u] = i;
+                    if (k0 + u < w) {
+                        const int64_t slot = soff + (int64_t)(k0 + u) * 64 + lane;
+                        int32_t j;
+                        if constexpr (CM == COL_GLOBAL32) j = col32[slot];
+                        else j = i + (int32_t)(int16_t)col16[slot];
+                        jx[u] = j == i ? n + i : j;
+                    }
                 }
-                G[slot] -= acc;
+                for (int32_t m = 0; m < L; ++m) {
+                    const int64_t base = (int64_t)m * n;
+                    const double mu = Mg[base + i];
+                    double xv[KB];
+#pragma unroll
+                    for (int u = 0; u < KB; ++u)
+                        if (k0 + u < w) xv[u] = Xg[base + jx[u]];
+#pragma unroll
+                    for (int u = 0; u < KB; ++u)
+                        if (k0 + u < w) acc[u] = __builtin_fma(mu, xv[u], acc[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < KB; ++u)
+                    if (k0 + u < w) {
+                        const int64_t slot = soff + (int64_t)(k0 + u) * 64 + lane;
+                        Gg[slot] -= acc[u];
+                    }
             }
         }
     }
