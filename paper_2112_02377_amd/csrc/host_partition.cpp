@@ -143,9 +143,14 @@ Partition make_partition(const Csr& a, int mode, int32_t P, const int32_t* sub_g
     out.bounds.insert(out.bounds.end(), sub_int_ptr.begin(), sub_int_ptr.end());
     out.bounds.insert(out.bounds.end(), sub_ifc_ptr.begin(), sub_ifc_ptr.end());
     out.bounds.insert(out.bounds.end(), part_sub_ptr.begin(), part_sub_ptr.end());
+    // a part owns one interior range and one interface range (its subdomains
+    // are consecutive); tiles stay inside one of them but may cross the
+    // subdomains within it, which avoids a partial tile per subdomain section
     out.cuts.clear();
-    out.cuts.insert(out.cuts.end(), sub_int_ptr.begin(), sub_int_ptr.end());
-    out.cuts.insert(out.cuts.end(), sub_ifc_ptr.begin(), sub_ifc_ptr.end());
+    for (int32_t q = 0; q <= P; ++q) {
+        out.cuts.push_back(sub_int_ptr[part_sub_ptr[q]]);
+        out.cuts.push_back(sub_ifc_ptr[part_sub_ptr[q]]);
+    }
     std::sort(out.cuts.begin(), out.cuts.end());
     out.cuts.erase(std::unique(out.cuts.begin(), out.cuts.end()), out.cuts.end());
     out.n_interior = n_int;

@@ -1,5 +1,6 @@
 // Tile planner: cuts the permuted matrix into tiles (contiguous row ranges
-// that never straddle a partition or subdomain boundary), each tile into
+// that never straddle a partition boundary, nor for substructuring the
+// boundary between a partition's interior and interface rows), each tile into
 // 64-row slices stored column-major and padded to the slice's longest row,
 // and -- for the staged modes -- lists the x entries each tile references
 // (its footprint) as runs of consecutive columns, with every column index

@@ -22,8 +22,10 @@ std::mutex g_cache_mutex;
 struct Cand {
     int32_t tile_rows, block;
 };
-const Cand kCands[] = {{256, 256}, {512, 256}, {1024, 256}, {2048, 256}, {512, 128},
-                       {512, 512}, {1024, 512}, {2048, 512}, {4096, 512}};
+// small tiles fill the chip on small systems (a tile is one workgroup per
+// sweep), large ones cut per-tile overhead on large systems
+const Cand kCands[] = {{64, 64},    {128, 64},   {128, 128},  {256, 128},  {256, 256},  {512, 256}, {1024, 256},
+                       {2048, 256}, {512, 128},  {512, 512},  {1024, 512}, {2048, 512}, {4096, 512}};
 
 std::string cache_key(const Handle& h)
 {

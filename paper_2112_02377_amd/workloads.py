@@ -185,6 +185,63 @@ def fe27(N: int = 96, workload: int = 3, drop: float = 0.1) -> CSRSystem:
 
 
 # --------------------------------------------------------------------------
+# Trilinear (Q1) finite-element Laplacian on the unit cube: the discretisation
+# behind the paper's Set-1 matrices (section 6: -Laplace(u) = f on [0,1]^3,
+# u = 0 on the boundary, f = cos(x + y), uniform hexahedral mesh)
+# --------------------------------------------------------------------------
+
+def fe_q1_cube(N: int) -> CSRSystem:
+    """Q1 stiffness matrix and load on an N^3 node mesh of the unit cube
+    (h = 1/(N-1); N = 33 and N = 65 give the node counts of the paper's
+    luf_cube-35937 and luf_cube-274625).  Deterministic (no draws).
+
+    Rows are the N^3 nodes, x fastest.  A boundary node's row is the identity
+    (u = 0 there, b = 0).  An interior node couples to the interior nodes of
+    its 3x3x3 neighbourhood (boundary columns are eliminated, their values
+    being 0) with the element stiffness summed over the 8 cubes around it:
+    8h/3 on the diagonal, 0 for the 6 face neighbours (kept as stored zeros,
+    as an assembled matrix holds them), -h/6 for the 12 edge neighbours and
+    -h/12 for the 8 corner neighbours.  The load is the consistent mass
+    product b_i = sum_j m_ij f(x_j) over the whole neighbourhood, with the
+    tensor-product mass m_ij = w(dx) w(dy) w(dz), w(0) = 2h/3, w(+-1) = h/6,
+    summed in ascending column order."""
+    n = N ** 3
+    h = 1.0 / (N - 1)
+    r = np.arange(n, dtype=np.int64)
+    i, j, k = r % N, (r // N) % N, r // (N * N)
+    interior = (i > 0) & (i < N - 1) & (j > 0) & (j < N - 1) & (k > 0) & (k < N - 1)
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]   # ascending columns
+    stiff = {0: 8.0 * h / 3.0, 1: 0.0, 2: -h / 6.0, 3: -h / 12.0}
+    wt = {0: 2.0 * h / 3.0, 1: h / 6.0, -1: h / 6.0}
+    f = np.cos(i * h + j * h)
+    b = np.zeros(n)
+    cols, vals, ok_all = [], [], []
+    for dx, dy, dz in offs:
+        nb = r + dx + N * dy + N * N * dz
+        ii, jj, kk = i + dx, j + dy, k + dz
+        nb_int = (ii > 0) & (ii < N - 1) & (jj > 0) & (jj < N - 1) & (kk > 0) & (kk < N - 1)
+        if (dx, dy, dz) == (0, 0, 0):
+            ok = np.ones(n, dtype=bool)                   # every row holds its diagonal
+            vals.append(np.where(interior, stiff[0], 1.0))
+        else:
+            ok = interior & nb_int
+            vals.append(np.full(n, stiff[abs(dx) + abs(dy) + abs(dz)]))
+        ok_all.append(ok)
+        cols.append(np.where(ok, nb, 0))
+        w = wt[dx] * wt[dy] * wt[dz]
+        b = b + np.where(interior, w * f[np.clip(nb, 0, n - 1)], 0.0)
+    okm = np.stack(ok_all, axis=1)                    # [n, 27], ascending columns per row
+    colm = np.stack(cols, axis=1)
+    valm = np.stack(vals, axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(okm.sum(axis=1), out=row_ptr[1:])
+    sysm = CSRSystem(row_ptr.astype(np.int32), colm[okm].astype(np.int32), valm[okm].astype(np.float64),
+                     b[None, :].copy(), grid=(N, N, N))
+    sysm.extra.update(h=h, interior=interior)
+    return sysm
+
+
+# --------------------------------------------------------------------------
 # Variable-coefficient diffusion (workloads 4 and 5)
 # --------------------------------------------------------------------------
 
