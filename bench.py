@@ -50,12 +50,16 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "launch.h")
+
+
 def src_digest():
+    """Digest of the device code: the kernel source and the headers of its
+    launch interface (host-only sources do not change what a kernel does)."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2112_02377_amd", "csrc"))):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(ROOT, "paper_2112_02377_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_02377_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -108,7 +112,8 @@ def secondary(B, W, torch, stream, with_oracle=True):
     systems x 4 right-hand sides, to 1e-8) against 256 separate solves, and
     the adjoint (64^3 diffusion, K = 400, checkpoint every 20) against its
     forward sweeps; then the Q1 FE stand-ins of the paper's Set-1 cubes solved
-    with its stop test, beside its iteration counts and CPU-cluster times.
+    with its stop test, beside its iteration counts and CPU-cluster times, and
+    the weighted partitioners against equal-row bands.
     Times are HIP-event times on the handles' stream."""
     out = {}
     sc = stream.cuda_stream
@@ -189,7 +194,47 @@ def secondary(B, W, torch, stream, with_oracle=True):
     B.jac_destroy(h)
     # -- the paper's Set-1 cubes (Q1 FE stand-ins) with its stop test
     out["paper_set1"] = set1(B, W, torch, stream)
+    # -- weighted partitions against equal-row bands
+    out["partitions"] = partitions(B, W, torch, stream)
     return out
+
+
+def partitions(B, W, torch, stream):
+    """Equal-row bands against nnz-weighted bands and the weighted graph
+    partition (section 4.2.2's load-balanced split): receive-list volume (the
+    per-sweep exchange of a multi-device run), stored-entry imbalance, host
+    partitioning time, and the one-GPU sweep time of the sparsity-pattern
+    band-row split on each (64 parts; 128^3 Laplacian and the 96^3 27-point
+    matrix)."""
+    import numpy as np
+    sc = stream.cuda_stream
+    res = {}
+    for name, s, K in (("laplace7_128", W.laplace7(128, workload=2), 500), ("fe27_96", W.fe27(96, workload=3), 300)):
+        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+        nnz_row = np.diff(s.row_ptr)
+        r = {}
+        for label, part in (("equal_rows", B.PART_ROWS), ("equal_nnz", B.PART_NNZ), ("graph", B.PART_GRAPH)):
+            B.jac_set_option(h, B.JAC_OPT_PARTITIONER, part)
+            t0 = time.perf_counter()
+            B.jac_partition(h, B.JAC_BANDROW_SP, 64)
+            t_part = time.perf_counter() - t0
+            got = B.jac_get_partition(h)
+            owner = np.zeros(s.n, dtype=np.int64)
+            owner[got["perm"]] = np.searchsorted(got["bounds"], np.arange(s.n), side="right") - 1
+            w = np.bincount(owner, weights=nnz_row, minlength=64)
+            B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
+            B.jac_set_x(h, None)
+            B.jac_sweep(h, 20)
+            B.jac_sweep(h, K)
+            info = B.jac_get_info(h)
+            B.jac_set_option(h, B.JAC_OPT_TIMING, 0)
+            r[label] = {"halo_entries": int(info["halo_entries"]), "nnz_imbalance": round(float(w.max() / w.mean()), 4),
+                        "partition_s": round(t_part, 2),
+                        "us_per_sweep": round(info["last_loop_ms"] * 1e3 / K, 3)}
+        r["n"], r["nnz"] = s.n, s.nnz
+        res[name] = r
+        B.jac_destroy(h)
+    return res
 
 
 # The paper's p = 1 iteration count and solver time, and its p = 64 solver

@@ -84,9 +84,17 @@ typedef enum {
     JAC_OPT_INNER_TOL = 6,   /* FP32 refinement: inner relative residual, x1e-9     */
     JAC_OPT_INNER_MAX = 7,   /* FP32 refinement: max inner sweeps per outer step    */
     JAC_OPT_CKPT_MEM_MB = 8, /* adjoint: cap on segment buffers (MiB)               */
-    JAC_OPT_TIMING = 9       /* 1 = time each sweep loop with HIP events on the
+    JAC_OPT_TIMING = 9,      /* 1 = time each sweep loop with HIP events on the
                                 handle's stream (jac_info.last_loop_ms); the call
                                 then waits for the loop to finish                  */
+    JAC_OPT_PARTITIONER = 10 /* how jac_partition forms parts / subdomains:
+                                0 = equal row counts and grid blocks (default);
+                                1 = equal stored-entry counts (contiguous bands;
+                                    JAC_SUBSTRUCT without a grid: contiguous
+                                    blocks of equal stored entries);
+                                2 = weighted graph partition (jac_graph_partition:
+                                    parts of the band-row modes, subdomains of
+                                    JAC_SUBSTRUCT), rows renumbered part by part */
 } jac_option;
 
 typedef struct {
@@ -133,7 +141,13 @@ jac_status jac_set_rhs(jac_handle h, const double *b_dev);
 jac_status jac_set_grid(jac_handle h, int32_t nx, int32_t ny, int32_t nz);
 
 /* Split the matrix into nparts parts (section 4).  Band boundaries are
- * floor(p*n/nparts) (section 4.2).  For JAC_SUBSTRUCT, sub_grid = {sx,sy,sz}
+ * floor(p*n/nparts) (section 4.2); JAC_OPT_PARTITIONER = 1 puts them where
+ * the stored entries before them reach p/nparts of all (the last row r with
+ * nnz(rows < r) * nparts <= p * nnz, which is floor(p*n/nparts) when every
+ * row holds the same count); JAC_OPT_PARTITIONER = 2 takes the parts
+ * from jac_graph_partition and numbers the rows part by part, ascending
+ * original index within a part (section 4.2.2, load-balanced bands that need
+ * not be contiguous).  For JAC_SUBSTRUCT, sub_grid = {sx,sy,sz}
  * gives sx*sy*sz subdomains (NULL: nparts contiguous subdomains, one per
  * part), grouped into parts by the same floor rule; a node is interface iff
  * a neighbour in A or A^T lies in another subdomain; the new order is the
@@ -204,6 +218,21 @@ jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double
  * fastest (x is restored afterwards).  The choice is cached on disk under
  * $JAC_TUNE_CACHE (if set), keyed by the matrix shape and split. */
 jac_status jac_autotune(jac_handle h, int32_t sweeps_per_trial);
+
+/* Host only (no device, no handle): split the graph of a sparse pattern into
+ * nparts parts of about equal weight with few cut edges -- the partition the
+ * paper proposes for load-balanced band rows (section 4.2.2: vertex i weighs
+ * the number of stored entries of row i, edges are the off-diagonal entries
+ * of A + A^T) and the role METIS plays for its substructuring (section 4.3).
+ * Multilevel recursive bisection (heavy-edge matching, greedy growing,
+ * Fiduccia-Mattheyses refinement), deterministic: the same pattern always
+ * gives the same parts; every part is non-empty and its weight stays within
+ * about 5% of total/nparts plus one row.  row_ptr[n+1], col_idx[nnz] 0-based
+ * (diagonals optional); part_out[n] receives the part of each row, in
+ * [0, nparts).  JAC_E_INVALID if nparts is outside [1, n] or the pattern is
+ * malformed. */
+jac_status jac_graph_partition(int32_t n, const int32_t *row_ptr_host, const int32_t *col_idx_host, int32_t nparts,
+                               int32_t *part_out_host);
 
 jac_status jac_set_option(jac_handle h, jac_option opt, int64_t value);
 jac_status jac_get_option(jac_handle h, jac_option opt, int64_t *value);

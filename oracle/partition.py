@@ -28,6 +28,16 @@ Rules (paper section 4; readings where the paper is silent are marked):
   another subdomain.  New order: interiors of subdomain 0..S-1, each ascending
   by original index, then all interface nodes sorted by (subdomain, index).
   Partition q owns subdomains [floor(q*S/P), floor((q+1)*S/P)).
+* Weighted variants (section 4.2.2 proposes weighting row i by its number of
+  stored entries; section 4.3 takes subdomains from a graph partitioner):
+  ``weights="nnz"`` puts band boundary p (and, without a grid, subdomain
+  boundary s) at the largest r with nnz(rows < r) * P <= p * nnz, which is
+  floor(p*n/P) when all rows hold the same count.  ``part_map`` supplies the
+  part of every row for the band-row modes (new order: rows part by part,
+  ascending index inside a part) and ``sub_map`` the subdomain of every node
+  for substructuring; the graph partitioner that produces such maps is a
+  heuristic with many valid answers and is checked by its properties, not
+  here.
 """
 from __future__ import annotations
 
@@ -40,6 +50,17 @@ def band_bounds(n: int, P: int) -> np.ndarray:
     """floor(p*n/P) for p = 0..P (int64 arithmetic, no overflow)."""
     p = np.arange(P + 1, dtype=np.int64)
     return (p * int(n)) // int(P)
+
+
+def nnz_bounds(row_ptr, P: int) -> np.ndarray:
+    """Largest r with nnz(rows < r) * P <= p * nnz, for p = 0..P."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    W = int(rp[-1])
+    out = np.zeros(P + 1, dtype=np.int64)
+    for p in range(P + 1):
+        # rp[r] is nnz(rows < r); rp is non-decreasing
+        out[p] = np.searchsorted(rp * P, p * W, side="right") - 1
+    return out
 
 
 def band_of(index: np.ndarray, bounds: np.ndarray) -> np.ndarray:
@@ -134,7 +155,8 @@ def permute_csr(row_ptr, col_idx, vals, perm: np.ndarray):
             None if vals is None else vals[src][order])
 
 
-def partition(row_ptr, col_idx, mode: int, P: int, grid=None, sub_grid=None) -> dict:
+def partition(row_ptr, col_idx, mode: int, P: int, grid=None, sub_grid=None, weights: str = "rows",
+              part_map=None, sub_map=None) -> dict:
     """Partition an n x n CSR pattern into P parts.
 
     Returns a dict with ``perm`` (new -> old), ``bounds`` (JB/JBO: band
@@ -146,13 +168,20 @@ def partition(row_ptr, col_idx, mode: int, P: int, grid=None, sub_grid=None) -> 
     if P < 1 or P > max(n, 1):
         raise ValueError("nparts out of range")
     if mode in (JB, JBO):
-        perm = np.arange(n, dtype=np.int64)
-        bounds = band_bounds(n, P)
-        owner = band_of(perm, bounds)
+        if part_map is not None:
+            part = np.asarray(part_map, dtype=np.int64)
+            perm = np.lexsort((np.arange(n), part))            # by part, then index
+            bounds = np.zeros(P + 1, dtype=np.int64)
+            np.cumsum(np.bincount(part, minlength=P), out=bounds[1:])
+        else:
+            perm = np.arange(n, dtype=np.int64)
+            bounds = nnz_bounds(row_ptr, P) if weights == "nnz" else band_bounds(n, P)
+        owner = band_of(np.arange(n), bounds)
         if mode == JB:
             rptr, ridx = np.zeros(P + 1, dtype=np.int32), np.zeros(0, dtype=np.int32)
         else:
-            rptr, ridx = recv_lists(row_ptr, col_idx, owner, P)
+            new_rp, new_ci, _ = permute_csr(row_ptr, col_idx, None, perm)
+            rptr, ridx = recv_lists(new_rp, new_ci, owner, P)
         return dict(perm=perm.astype(np.int32), bounds=bounds.astype(np.int32), owner=owner,
                     recv_ptr=rptr, recv_idx=ridx)
     if mode != JSS:
@@ -162,7 +191,12 @@ def partition(row_ptr, col_idx, mode: int, P: int, grid=None, sub_grid=None) -> 
     S = int(np.prod(sub_grid))
     if S < P:
         raise ValueError("fewer subdomains than parts")
-    sub = subdomain_map(n, grid, sub_grid)
+    if sub_map is not None:
+        sub = np.asarray(sub_map, dtype=np.int64)
+    elif grid is None and weights == "nnz":
+        sub = band_of(np.arange(n), nnz_bounds(row_ptr, S))
+    else:
+        sub = subdomain_map(n, grid, sub_grid)
     ifc = interface_mask(row_ptr, col_idx, sub)
     idx = np.arange(n, dtype=np.int64)
     interior = idx[~ifc]

@@ -24,11 +24,13 @@ JAC_BANDROW, JAC_BANDROW_SP, JAC_SUBSTRUCT = 1, 2, 3
 JAC_NORM_L2_REL, JAC_NORM_INF_ABS = 0, 1
 JAC_FP64, JAC_FP32_REFINE = 0, 1
 (JAC_OPT_TILE_ROWS, JAC_OPT_BLOCK, JAC_OPT_LDS_ELEMS, JAC_OPT_LOOP, JAC_OPT_WG_PER_CU, JAC_OPT_INNER_TOL,
- JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING) = range(1, 10)
+ JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING, JAC_OPT_PARTITIONER) = range(1, 11)
+PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
-           "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error"]
+           "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
+           "jac_graph_partition"]
 
 
 class jac_info(C.Structure):
@@ -80,6 +82,7 @@ def lib():
             "jac_set_option": [_vp, C.c_int, C.c_int64],
             "jac_get_option": [_vp, C.c_int, _i64p],
             "jac_get_info": [_vp, C.POINTER(jac_info)],
+            "jac_graph_partition": [C.c_int32, _i32p, _i32p, C.c_int32, _i32p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -226,6 +229,17 @@ def jac_adjoint(h, K, ckpt_every, gx_dev, gb_dev=None, gvals_dev=None):
 
 def jac_autotune(h, sweeps_per_trial=20):
     return _check(lib().jac_autotune(h, int(sweeps_per_trial)))
+
+
+def jac_graph_partition(row_ptr, col_idx, nparts):
+    """Host-only weighted graph partition of a CSR pattern; returns part[n]."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.shape[0] - 1
+    part = np.zeros(max(n, 0), dtype=np.int32)
+    _check(lib().jac_graph_partition(n, rp.ctypes.data_as(_i32p), ci.ctypes.data_as(_i32p), int(nparts),
+                                     part.ctypes.data_as(_i32p)))
+    return part
 
 
 def jac_set_option(h, opt, value):

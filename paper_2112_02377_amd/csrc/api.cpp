@@ -94,7 +94,7 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
         xsave.alloc((size_t)a.n * nrhs * sizeof(double));
         get_x_dev(static_cast<double*>(xsave.p));
     }
-    Partition np = make_partition(a, mode, nparts, sub_grid, has_grid ? grid : nullptr);
+    Partition np = make_partition(a, mode, nparts, sub_grid, has_grid ? grid : nullptr, opt.partitioner);
     std::vector<int64_t> src;
     Csr pa = permute(a, np.perm, np.iperm, &src);
     PlanParams prm;
@@ -678,6 +678,9 @@ jac_status jac_set_option(jac_handle h, jac_option opt, int64_t v)
         case JAC_OPT_TIMING:
             if (v != 0 && v != 1) fail(JAC_E_INVALID, "timing: 0 or 1");
             o.timing = (int32_t)v; break;
+        case JAC_OPT_PARTITIONER:
+            if (v < 0 || v > 2) fail(JAC_E_INVALID, "partitioner: 0, 1 or 2");
+            o.partitioner = (int32_t)v; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -699,6 +702,7 @@ jac_status jac_get_option(jac_handle h, jac_option opt, int64_t* v)
         case JAC_OPT_INNER_MAX: *v = o.inner_max; break;
         case JAC_OPT_CKPT_MEM_MB: *v = o.ckpt_mb; break;
         case JAC_OPT_TIMING: *v = o.timing; break;
+        case JAC_OPT_PARTITIONER: *v = o.partitioner; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;

@@ -36,6 +36,7 @@ struct Options {
     int32_t inner_max = 256;
     int64_t ckpt_mb = 4096;
     int32_t timing = 0;
+    int32_t partitioner = 0;
 };
 
 struct DeviceArrays {

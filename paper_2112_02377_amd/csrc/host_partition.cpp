@@ -14,6 +14,11 @@
 //    original index), then the interface sorted by (subdomain, index)
 //    (section 4.3, block form with the interface block last);
 //  * part q owns subdomains [floor(q*S/P), floor((q+1)*S/P)).
+//
+// Optional partitioners (section 4.2.2 proposes weighting each row by its
+// stored entries; section 4.3 takes subdomains from a graph partitioner):
+// contiguous blocks of equal stored-entry count, or the weighted graph
+// partition of host_graph.cpp, whose parts are numbered part by part.
 #include <algorithm>
 #include <numeric>
 
@@ -60,25 +65,62 @@ static void receive_lists(const Csr& a, const std::vector<int32_t>& owner, int32
     for (int32_t p = 0; p < P; ++p) out.recv_ptr[p + 1] += out.recv_ptr[p];
 }
 
-Partition make_partition(const Csr& a, int mode, int32_t P, const int32_t* sub_grid, const int32_t* grid)
+// Edges of P contiguous blocks of equal stored-entry count: block p starts at
+// the last row r with nnz(rows < r) * P <= p * nnz (with equal rows this is
+// floor(p*n/P), the equal-row rule).
+static void nnz_edges(const Csr& a, int32_t P, std::vector<int32_t>& edges)
+{
+    const int64_t W = a.rp[a.n];
+    edges.assign((size_t)P + 1, 0);
+    int32_t r = 0;
+    for (int32_t p = 0; p <= P; ++p) {
+        while (r < a.n && (int64_t)a.rp[r + 1] * P <= (int64_t)p * W) ++r;
+        edges[p] = r;
+    }
+}
+
+Partition make_partition(const Csr& a, int mode, int32_t P, const int32_t* sub_grid, const int32_t* grid,
+                         int partitioner)
 {
     const int32_t n = a.n;
     if (P < 1 || (n > 0 && P > n) || (n == 0 && P != 1)) fail(JAC_E_INVALID, "nparts out of range");
+    if (partitioner < 0 || partitioner > 2) fail(JAC_E_INVALID, "unknown partitioner");
     Partition out;
     out.mode = mode;
     out.nparts = P;
     if (mode == JAC_BANDROW || mode == JAC_BANDROW_SP) {
         out.perm.resize(n);
-        std::iota(out.perm.begin(), out.perm.end(), 0);
-        out.iperm = out.perm;
-        out.bounds.resize((size_t)P + 1);
-        for (int32_t p = 0; p <= P; ++p) out.bounds[p] = (int32_t)band_edge(p, n, P);
+        out.bounds.assign((size_t)P + 1, 0);
+        if (partitioner == 2) {
+            // graph parts; rows part by part, ascending original index inside
+            std::vector<int32_t> part;
+            graph_partition(a, P, part);
+            for (int32_t r = 0; r < n; ++r) out.bounds[part[r] + 1]++;
+            for (int32_t p = 0; p < P; ++p) out.bounds[p + 1] += out.bounds[p];
+            std::vector<int32_t> fill(out.bounds.begin(), out.bounds.end() - 1);
+            for (int32_t r = 0; r < n; ++r) out.perm[fill[part[r]]++] = r;
+        } else {
+            std::iota(out.perm.begin(), out.perm.end(), 0);
+            if (partitioner == 1) nnz_edges(a, P, out.bounds);
+            else
+                for (int32_t p = 0; p <= P; ++p) out.bounds[p] = (int32_t)band_edge(p, n, P);
+        }
+        out.iperm.assign(n, 0);
+        for (int32_t r = 0; r < n; ++r) out.iperm[out.perm[r]] = r;
         out.cuts = out.bounds;
         out.owner.resize(n);
         for (int32_t p = 0; p < P; ++p)
             for (int32_t r = out.bounds[p]; r < out.bounds[p + 1]; ++r) out.owner[r] = p;
         if (mode == JAC_BANDROW_SP) {
-            receive_lists(a, out.owner, P, out);
+            if (partitioner == 2) {
+                Csr pattern;
+                pattern.n = n;
+                pattern.rp = a.rp;
+                pattern.ci = a.ci;
+                receive_lists(permute(pattern, out.perm, out.iperm, nullptr), out.owner, P, out);
+            } else {
+                receive_lists(a, out.owner, P, out);
+            }
         } else {
             out.recv_ptr.assign((size_t)P + 1, 0);
         }
@@ -92,7 +134,9 @@ Partition make_partition(const Csr& a, int mode, int32_t P, const int32_t* sub_g
     if (S64 < P || S64 > (int64_t)std::max(n, 1)) fail(JAC_E_INVALID, "need nparts <= subdomains <= n");
     const int32_t S = (int32_t)S64;
     std::vector<int32_t> sub(n);
-    if (grid) {
+    if (partitioner == 2) {
+        graph_partition(a, S, sub);
+    } else if (grid) {
         const int64_t nx = grid[0], ny = grid[1], nz = grid[2];
         if (nx * ny * nz != n) fail(JAC_E_INVALID, "grid does not match n");
         if (sx > nx || sy > ny || sz > nz) fail(JAC_E_INVALID, "more subdomains than nodes along an axis");
@@ -105,8 +149,12 @@ Partition make_partition(const Csr& a, int mode, int32_t P, const int32_t* sub_g
             sub[r] = bx[i] + sx * (by[j] + sy * bz[k]);
         }
     } else {
+        std::vector<int32_t> edges((size_t)S + 1);
+        if (partitioner == 1) nnz_edges(a, S, edges);
+        else
+            for (int32_t s = 0; s <= S; ++s) edges[s] = (int32_t)band_edge(s, n, S);
         for (int32_t s = 0; s < S; ++s)
-            for (int64_t r = band_edge(s, n, S); r < band_edge(s + 1, n, S); ++r) sub[r] = s;
+            for (int32_t r = edges[s]; r < edges[s + 1]; ++r) sub[r] = s;
     }
     std::vector<uint8_t> ifc(n, 0);
     for (int32_t r = 0; r < n; ++r)

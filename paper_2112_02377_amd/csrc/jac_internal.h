@@ -49,7 +49,13 @@ struct Partition {
     int32_t n_interior = -1;
 };
 
-Partition make_partition(const Csr& a, int mode, int32_t nparts, const int32_t* sub_grid, const int32_t* grid);
+// partitioner: 0 = equal rows / grid blocks, 1 = equal stored entries
+// (contiguous), 2 = weighted graph partition (see jac_graph_partition).
+Partition make_partition(const Csr& a, int mode, int32_t nparts, const int32_t* sub_grid, const int32_t* grid,
+                         int partitioner = 0);
+
+// Weighted graph partition of a's pattern into k parts (host_graph.cpp).
+void graph_partition(const Csr& a, int32_t k, std::vector<int32_t>& part);
 
 // P A P^T with ascending columns; src[p] = index in a of new entry p.
 Csr permute(const Csr& a, const std::vector<int32_t>& perm, const std::vector<int32_t>& iperm,
