@@ -170,7 +170,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
 
         // forward from x_0 = 0, one launch per sweep on the handle's three
         // iterate buffers (x_k in buffer k mod 3); x_{jc} kept as checkpoint j
-        void* fn = sweep_kernel(false, 1, h.plan.colfmt, false);
+        void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0);
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);
         const int grid = std::max(h.plan.ntiles, 1) + 1;

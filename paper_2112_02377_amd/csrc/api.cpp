@@ -310,14 +310,83 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
             if (!e) JAC_HIP(hipEventCreate(&e));
         JAC_HIP(hipEventRecord(h.ev[0], st));
     }
-    if (h.opt.loop == 1 || nsys > 1) {
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, true);
+    if (h.opt.loop == 1) {
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 1);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, nsys);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, work);
         h.last_grid = grid;
         launch_loop(fn, grid, block, lds, st, p, fp_bytes, runs, true);
+    } else if (nsys > 1) {
+        // One launch per sweep over the systems still running.  The host
+        // reads the states one chunk of launches behind (so the device never
+        // waits for it) and drops stopped systems from the list; a stopped
+        // system still on the list costs its tiles an early return.
+        if (!solve) fail(JAC_E_INVALID, "several systems are swept in solve mode only");
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 2);
+        const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
+        const size_t wl_ints = 2 * (size_t)nsys + 1;
+        const size_t host_bytes = (size_t)nsys * sizeof(SysState) + 2 * wl_ints * sizeof(int32_t);
+        if (h.d.batch_host.bytes < host_bytes) {
+            h.d.batch_host.reset();
+            JAC_HIP(hipHostMalloc(&h.d.batch_host.p, host_bytes, hipHostMallocDefault));
+            h.d.batch_host.bytes = host_bytes;
+            h.d.batch_host.pinned = true;
+        }
+        h.d.batch_wl.ensure(wl_ints * sizeof(int32_t));
+        SysState* states = static_cast<SysState*>(h.d.batch_host.p);
+        int32_t* stage = reinterpret_cast<int32_t*>(states + nsys);
+        const int32_t* d_wl = static_cast<const int32_t*>(h.d.batch_wl.p);
+        if (!h.pev) JAC_HIP(hipEventCreateWithFlags(&h.pev, hipEventDisableTiming));
+        // two staging copies: the one written next is never the source of a
+        // copy the stream has not run yet (the host waits on the event
+        // recorded after the previous copy before writing it again)
+        int buf = 0;
+        auto upload = [&](const std::vector<int32_t>& act) -> int32_t {
+            int32_t* w = stage + (size_t)buf * wl_ints;
+            buf ^= 1;
+            const int32_t na = (int32_t)act.size();
+            w[na] = 0;
+            for (int32_t i = 0; i < na; ++i) {
+                w[i] = act[i];
+                w[na + 1 + i] = w[na + i] + (tile_base[act[i] + 1] - tile_base[act[i]]);
+            }
+            JAC_HIP(hipMemcpyAsync(h.d.batch_wl.p, w, (2 * (size_t)na + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   st));
+            return w[2 * na];
+        };
+        std::vector<int32_t> act;
+        for (int32_t s = 0; s < nsys; ++s)
+            if (tile_base[s + 1] > tile_base[s]) act.push_back(s);
+        int32_t items = upload(act);
+        h.last_grid = items + (int)act.size();
+        const int chunk = 64;
+        int32_t k = 0;
+        bool pending = false, all_done = act.empty();
+        while (!all_done && k <= kend) {
+            const int32_t e = std::min<int32_t>(kend + 1, k + chunk);
+            const int32_t na = (int32_t)act.size();
+            for (; k < e; ++k) launch_sweep_multi(fn, items + na, block, lds, st, p, k, d_wl, na, fp_bytes, runs);
+            if (pending) {
+                JAC_HIP(hipEventSynchronize(h.pev));
+                std::vector<int32_t> next;
+                for (int32_t s : act)
+                    if (states[s].done_k == kRunning) next.push_back(s);
+                if (next.empty()) {
+                    all_done = true;
+                    break;
+                }
+                if (next.size() != act.size()) {
+                    act.swap(next);
+                    items = upload(act);
+                }
+            }
+            JAC_HIP(hipMemcpyAsync(states, d_state.p, (size_t)nsys * sizeof(SysState), hipMemcpyDeviceToHost, st));
+            JAC_HIP(hipEventRecord(h.pev, st));
+            pending = true;
+        }
+        if (!all_done) launch_decide_multi(nrhs, st, p, kend);
     } else {
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, false);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 0);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
         const int grid = (int)std::max<int64_t>(1, work) + 1;      // + the deciding workgroup
         h.last_grid = grid;

@@ -49,6 +49,7 @@ struct DeviceArrays {
     DevMem poll;                           // pinned host word for stop polling
     DevMem sys, state, bar, bad, norm_part, bnorm;
     DevMem batch_sys, batch_state, batch_tile_base;
+    DevMem batch_wl, batch_host;           // system list (device), pinned states and list staging
     // FP32 refinement
     DevMem r32, d0, d1, d2, rpart;
     // adjoint: A^T slot map, A's global columns (staged plans), and the

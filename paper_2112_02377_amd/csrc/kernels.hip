@@ -390,6 +390,72 @@ __global__ void __launch_bounds__(512) k_decide(LoopParams P, int32_t k)
     decide<NRHS, false>(P, 0, k, P.sys[0], red);
 }
 
+// Sweep k of several systems in one launch.  The work list wl holds the ids
+// of the nact systems still running (ascending), then the prefix of their
+// tile counts (nact + 1 entries); workgroup j < items sweeps item j (tile
+// j - pref[i] of system ids[i]), and the nact workgroups after the items take
+// the stop decisions of sweep k - 1, one system each, exactly as the last
+// workgroup of a single-system launch does.  A system that stopped is
+// skipped by its tiles and left alone by its decider (the host drops it from
+// the list a little later).
+template <typename T, int NRHS, int CM>
+__global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, const int32_t* __restrict__ wl,
+                                                    int32_t nact, int32_t lds_fp_bytes, int32_t lds_runs)
+{
+    extern __shared__ __align__(16) char smem[];
+    T* lds_x = reinterpret_cast<T*>(smem);
+    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    int32_t* lds_ro = lds_rs + lds_runs;
+    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    const cptr<const int32_t> ids = (cptr<const int32_t>)wl;
+    const cptr<const int32_t> pref = (cptr<const int32_t>)(wl + nact);
+    const int32_t items = pref[nact];
+    const int32_t wg = (int32_t)blockIdx.x;
+    if (wg >= items) {
+        const int32_t s = ids[wg - items];
+        if (k > P.k0) decide<NRHS, false>(P, s, k - 1, P.sys[s], red);
+        return;
+    }
+    int32_t first, end, stride;
+    xcd_items(items, items, wg, first, end, stride);   // one item per workgroup
+    const bool is_max = P.norm_inf != 0;
+    for (int32_t j = first; j < end; j += stride) {
+        int32_t lo = 0, hi = nact - 1;                  // list entry holding item j
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (pref[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        const int32_t s = ids[lo], tile = j - pref[lo];
+        const SysDev& S = P.sys[s];
+        const SysState* sst = &P.st[s];
+        if (sst->done_k <= k) continue;
+        uint32_t frozen = 0;
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c)
+            if (sst->stop_k[c] < k) frozen |= 1u << c;
+        double acc[NRHS];
+#pragma unroll
+        for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
+        sweep_tile<T, NRHS, CM>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]), reinterpret_cast<T*>(S.x[(k + 1) % 3]),
+                                frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        block_reduce<NRHS>(acc, is_max, red);
+        if (threadIdx.x == 0) {
+            double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) part[(int64_t)tile * NRHS + c] = acc[c];
+        }
+    }
+}
+
+// Closing decisions of several systems (one workgroup each) on sweep k.
+template <int NRHS>
+__global__ void __launch_bounds__(512) k_decide_multi(LoopParams P, int32_t k)
+{
+    __shared__ double red[16 * 4];
+    const int32_t s = (int32_t)blockIdx.x;
+    if (s < P.nsys) decide<NRHS, false>(P, s, k, P.sys[s], red);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 residual for mixed-precision refinement: r = b - A x with the FP64
 // coefficients, written as FP32 (the right-hand side of the inner FP32
@@ -698,14 +764,18 @@ __global__ void k_colnorm_final(const double* __restrict__ part, int32_t nblocks
 // ---------------------------------------------------------------------------
 namespace {
 
+// loop: 0 = one launch per sweep, 1 = persistent loop, 2 = one launch per
+// sweep over a list of systems
 template <typename T, int NRHS, int CM>
-void* kfn(bool loop)
+void* kfn(int loop)
 {
-    return loop ? reinterpret_cast<void*>(&k_loop<T, NRHS, CM>) : reinterpret_cast<void*>(&k_sweep<T, NRHS, CM>);
+    if (loop == 1) return reinterpret_cast<void*>(&k_loop<T, NRHS, CM>);
+    if (loop == 2) return reinterpret_cast<void*>(&k_sweep_multi<T, NRHS, CM>);
+    return reinterpret_cast<void*>(&k_sweep<T, NRHS, CM>);
 }
 
 template <typename T, int NRHS>
-void* pick_cm(int colfmt, bool loop)
+void* pick_cm(int colfmt, int loop)
 {
     switch (colfmt) {
     case COL_GLOBAL32: return kfn<T, NRHS, COL_GLOBAL32>(loop);
@@ -716,7 +786,7 @@ void* pick_cm(int colfmt, bool loop)
 }
 
 template <typename T>
-void* pick(int nrhs, int colfmt, bool loop)
+void* pick(int nrhs, int colfmt, int loop)
 {
     switch (nrhs) {
     case 1: return pick_cm<T, 1>(colfmt, loop);
@@ -736,7 +806,7 @@ int grid1d(int64_t m, int block = 256)
 
 }  // namespace
 
-void* sweep_kernel(bool fp32, int nrhs, int colfmt, bool loop)
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop)
 {
     void* f = fp32 ? pick<float>(nrhs, colfmt, loop) : pick<double>(nrhs, colfmt, loop);
     if (!f) fail(JAC_E_INVALID, "no sweep kernel for this right-hand-side count / column format");
@@ -763,6 +833,24 @@ void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, Lo
 {
     void* args[] = {&p, &k, &lds_fp_bytes, &lds_runs};
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
+}
+
+void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
+                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs)
+{
+    void* args[] = {&p, &k, &wl, &nact, &lds_fp_bytes, &lds_runs};
+    JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
+}
+
+void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k)
+{
+    if (p.nsys < 1) return;
+    switch (nrhs) {
+    case 1: k_decide_multi<1><<<p.nsys, 256, 0, st>>>(p, k); break;
+    case 2: k_decide_multi<2><<<p.nsys, 256, 0, st>>>(p, k); break;
+    default: k_decide_multi<4><<<p.nsys, 256, 0, st>>>(p, k); break;
+    }
+    JAC_HIP(hipGetLastError());
 }
 
 void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k)

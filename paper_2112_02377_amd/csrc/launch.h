@@ -11,15 +11,19 @@
 namespace jac {
 
 // Kernel of the fused sweep for an element type, right-hand-side count
-// (1, 2 or 4), column format (ColFormat) and loop kind (persistent loop or
-// one launch per sweep).
-void* sweep_kernel(bool fp32, int nrhs, int colfmt, bool loop);
+// (1, 2 or 4), column format (ColFormat) and loop kind (0 = one launch per
+// sweep, 1 = persistent loop, 2 = one launch per sweep over a system list).
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop);
 size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys);
 void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int lds_fp_bytes,
                  int lds_runs, bool cooperative);
 void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
                    int lds_fp_bytes, int lds_runs);
 void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k);
+// several systems: wl = running system ids [nact] then their tile prefix [nact + 1]
+void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
+                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs);
+void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k);
 // mixed-precision refinement
 void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
                   float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs);

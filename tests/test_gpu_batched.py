@@ -1,5 +1,6 @@
-"""GPU: many uneven systems with several right-hand sides in one persistent
-launch, against separate solves and the CPU oracle."""
+"""GPU: many uneven systems with several right-hand sides solved together
+(one launch per global sweep, or one persistent launch), against separate
+solves and the CPU oracle."""
 import numpy as np
 import pytest
 
@@ -14,11 +15,14 @@ def small_batch(nsys=12, lo=5, hi=14):
     return W.diffusion_batch(nsys, workload=4, lo=lo, hi=hi)
 
 
-def test_batched_equals_separate_solves_and_oracle():
+@pytest.mark.parametrize("loop", [0, 1])
+def test_batched_equals_separate_solves_and_oracle(loop):
+    # loop 0: one launch per global sweep over the running systems; 1: one
+    # persistent launch
     need_gpu()
     b = B()
     systems = small_batch()
-    hs = [make(s, 1, 1) for s in systems]
+    hs = [make(s, 1, 1, opts={b.JAC_OPT_LOOP: loop}) for s in systems]
     st, sw, rr = b.jac_solve_batched(hs, 1e-8, 200000)
     assert st == b.JAC_OK
     xb = [get_x(h, s.n, 4) for h, s in zip(hs, systems)]
@@ -65,3 +69,24 @@ def test_persistent_loop_matches_per_launch_for_fixed_sweeps():
         out.append((get_x(h, s.n)[0], hist.cpu().numpy()))
         b.jac_destroy(h)
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("loop", [0, 1])
+def test_batched_maxit_exhausted_equals_separate_solves(loop):
+    # every column runs out of sweeps: statuses, counts, norms and iterates
+    # equal those of separate solves with the same cap
+    need_gpu()
+    b = B()
+    systems = small_batch(5, 8, 12)
+    hs = [make(s, 1, 1, opts={b.JAC_OPT_LOOP: loop}) for s in systems]
+    st, sw, rr = b.jac_solve_batched(hs, 1e-14, 150)
+    assert st == b.JAC_NOT_CONVERGED
+    for si, (h, s) in enumerate(zip(hs, systems)):
+        xb = get_x(h, s.n, 4)
+        h1 = make(s, 1, 1)
+        st1, sw1, rr1 = b.jac_solve(h1, 1e-14, 150)
+        assert st1 == b.JAC_NOT_CONVERGED
+        assert np.array_equal(sw[si], sw1) and np.array_equal(rr[si], rr1)
+        assert np.array_equal(xb, get_x(h1, s.n, 4))
+        b.jac_destroy(h1)
+        b.jac_destroy(h)
