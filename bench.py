@@ -112,8 +112,9 @@ def secondary(B, W, torch, stream, with_oracle=True):
     systems x 4 right-hand sides, to 1e-8) against 256 separate solves, and
     the adjoint (64^3 diffusion, K = 400, checkpoint every 20) against its
     forward sweeps; then the Q1 FE stand-ins of the paper's Set-1 cubes solved
-    with its stop test, beside its iteration counts and CPU-cluster times, and
-    the weighted partitioners against equal-row bands.
+    with its stop test, beside its iteration counts and CPU-cluster times, the
+    weighted partitioners against equal-row bands, and the asynchronous
+    relaxation against the synchronous solve.
     Times are HIP-event times on the handles' stream."""
     import numpy as np
     out = {}
@@ -204,7 +205,43 @@ def secondary(B, W, torch, stream, with_oracle=True):
     out["paper_set1"] = set1(B, W, torch, stream)
     # -- weighted partitions against equal-row bands
     out["partitions"] = partitions(B, W, torch, stream)
+    # -- asynchronous relaxation against the synchronous solve
+    out["async"] = async_vs_sync(B, W, torch, stream)
     return out
+
+
+def async_vs_sync(B, W, torch, stream):
+    """Time to solution and passes of the asynchronous relaxation (16 and 64
+    passes per launch between stop tests) against the synchronous solve's
+    sweeps, from x_0 = 0, on the 20^3 Laplacian (relative 2-norm 1e-8), the
+    Set-1 cubes (the paper's absolute infinity-norm test) and the 64^3
+    diffusion system (relative 2-norm 1e-8)."""
+    sc = stream.cuda_stream
+    cases = [("laplace7_20", W.laplace7(20, workload=1), B.JAC_BANDROW_SP, 4, None, B.JAC_NORM_L2_REL),
+             ("q1_cube_33", W.fe_q1_cube(33), B.JAC_SUBSTRUCT, 8, (2, 2, 2), B.JAC_NORM_INF_ABS),
+             ("q1_cube_65", W.fe_q1_cube(65), B.JAC_BANDROW_SP, 64, None, B.JAC_NORM_INF_ABS),
+             ("diffusion_64", W.diffusion_adjoint(64, workload=5), B.JAC_BANDROW_SP, 64, None, B.JAC_NORM_L2_REL)]
+    res = {}
+    for name, s, mode, P, sub, norm in cases:
+        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+        B.jac_set_grid(h, *s.grid)
+        B.jac_partition(h, mode, P, sub)
+        B.jac_set_x(h, None)
+        B.jac_solve(h, 1e-8, 1000000, norm)                          # warm
+        B.jac_set_x(h, None)
+        ms, (st, sw, rr) = _timed(torch, stream, lambda: B.jac_solve(h, 1e-8, 1000000, norm))
+        r = {"sync": {"sweeps": int(sw[0]), "ms": round(ms, 3), "res": float(rr[0])}}
+        for R in (16, 64):
+            B.jac_set_x(h, None)
+            B.jac_solve_async(h, 1e-8, 1000000, norm, R)            # warm
+            B.jac_set_x(h, None)
+            ms, (st, rd, rr) = _timed(torch, stream, lambda: B.jac_solve_async(h, 1e-8, 1000000, norm, R))
+            r[f"async_R{R}"] = {"passes": int(rd[0]), "ms": round(ms, 3), "res": float(rr[0]),
+                                "passes_over_sweeps": round(int(rd[0]) / max(int(sw[0]), 1), 3),
+                                "speedup_vs_sync": round(r["sync"]["ms"] / ms, 3)}
+        res[name] = r
+        B.jac_destroy(h)
+    return res
 
 
 def partitions(B, W, torch, stream):

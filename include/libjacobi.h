@@ -203,6 +203,23 @@ jac_status jac_solve(jac_handle h, double tol, int32_t maxit, jac_norm norm, jac
 jac_status jac_solve_batched(const jac_handle *hs, int32_t nsys, double tol, int32_t maxit,
                              int32_t *sweeps_out_host, double *relres_out_host);
 
+/* Asynchronous (chaotic) relaxation from the current x, the variant the
+ * paper proposes for lifting the per-iteration synchronisation (section 6,
+ * discussion of the results).  Each launch runs rounds_per_check passes in
+ * which every workgroup updates its own tiles' rows of x in place from the
+ * values of x it finds (no barrier between workgroups; device-coherent loads
+ * and stores of x); between launches the residual b - A x of the quiescent x
+ * is evaluated with the same norm and test as jac_solve.  Converges for
+ * matrices with rho(|D^{-1}(L+U)|) < 1 (e.g. diagonally dominant ones).
+ * rounds_out[nrhs] = passes run (a multiple of rounds_per_check unless maxit
+ * ends it), relres_out[nrhs] = the norms of the returned x; either may be
+ * NULL.  JAC_NOT_CONVERGED once maxit passes are spent, JAC_E_DIVERGED on a
+ * non-finite or exploding norm.  Not bit-reproducible: which values a tile
+ * reads depends on timing; the returned x always passed the test evaluated
+ * on it. */
+jac_status jac_solve_async(jac_handle h, double tol, int32_t maxit, jac_norm norm, int32_t rounds_per_check,
+                           int32_t *rounds_out, double *relres_out);
+
 /* Reverse-mode derivative of K sweeps from x_0 = 0 for right-hand side 0:
  * given gx_dev = dL/dx_K (n, original order), writes gb_dev = dL/db (n) and
  * gvals_dev = dL/dvals (nnz, caller's CSR entry order, diagonal included).

@@ -30,7 +30,7 @@ PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
            "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
-           "jac_graph_partition"]
+           "jac_graph_partition", "jac_solve_async"]
 
 
 class jac_info(C.Structure):
@@ -83,6 +83,7 @@ def lib():
             "jac_get_option": [_vp, C.c_int, _i64p],
             "jac_get_info": [_vp, C.POINTER(jac_info)],
             "jac_graph_partition": [C.c_int32, _i32p, _i32p, C.c_int32, _i32p],
+            "jac_solve_async": [_vp, C.c_double, C.c_int32, C.c_int, C.c_int32, _i32p, _f64p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -210,6 +211,18 @@ def jac_solve(h, tol, maxit, norm=JAC_NORM_L2_REL, prec=JAC_FP64, nrhs=None):
                          rr.ctypes.data_as(_f64p))
     _check(st)
     return st, sw, rr
+
+
+def jac_solve_async(h, tol, maxit, norm=JAC_NORM_L2_REL, rounds_per_check=16, nrhs=None):
+    """Returns (status, rounds[nrhs], relres[nrhs]); JAC_NOT_CONVERGED is returned, not raised."""
+    if nrhs is None:
+        nrhs = jac_get_info(h)["nrhs"]
+    rounds = np.zeros(nrhs, np.int32)
+    rr = np.zeros(nrhs, np.float64)
+    st = lib().jac_solve_async(h, float(tol), int(maxit), int(norm), int(rounds_per_check),
+                               rounds.ctypes.data_as(_i32p), rr.ctypes.data_as(_f64p))
+    _check(st)
+    return st, rounds, rr
 
 
 def jac_solve_batched(handles, tol, maxit):

@@ -56,6 +56,8 @@ struct DeviceArrays {
     // working buffers, kept between calls (grow-only)
     DevMem t_map, a_gcol;
     DevMem adj_ck, adj_X, adj_M, adj_lam0, adj_lam1, adj_carry, adj_gb, adj_G, adj_sys, adj_segs;
+    // asynchronous solve: descriptor, residual scratch, norms
+    DevMem async_sys, async_r32, async_norm;
 };
 
 struct Handle {

@@ -141,7 +141,21 @@ __device__ __forceinline__ void xcd_items(int32_t T, int32_t G, int32_t wg, int3
 // One tile of one sweep: stage the footprint (staged tiles), then one slice
 // of 64 rows per wavefront; accumulates the tile's residual norm partial.
 // ---------------------------------------------------------------------------
-template <typename T, int NRHS, int CM, bool RESID = false>
+// COH: x is read and written in place by other workgroups of the same launch
+// (asynchronous iteration): its loads and stores are device-coherent.
+template <typename V, bool COH>
+__device__ __forceinline__ V ldx(const V* p)
+{
+    if constexpr (COH) return __hip_atomic_load((gptr<const V>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *(gptr<const V>)p;
+}
+template <typename V>
+__device__ __forceinline__ void stx_dev(V* p, V v)
+{
+    __hip_atomic_store((gptr<V>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, int NRHS, int CM, bool RESID = false, bool COH = false>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
                                            bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
                                            int32_t* __restrict__ lds_ro, double (&acc)[NRHS],
@@ -150,7 +164,6 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     // RESID: no update; the residual is written rounded to FP32 into rout
     const gptr<float> rout = (gptr<float>)rout_;
     // every array below is device memory: global address space for the loads
-    const gptr<const T> x = (gptr<const T>)x_;
     const gptr<T> xn = (gptr<T>)xn_;
     const gptr<const T> val = (gptr<const T>)S.val;
     const gptr<const T> b = (gptr<const T>)S.b;
@@ -203,7 +216,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             for (int u = 0; u < SU; ++u) {
                 const int64_t g = (int64_t)(lds_rs[lo[u]] + (e[u] - lds_ro[lo[u]]));
 #pragma unroll
-                for (int c = 0; c < NRHS; ++c) v[u][c] = x[g * NRHS + c];
+                for (int c = 0; c < NRHS; ++c) v[u][c] = ldx<T, COH>(&x_[g * NRHS + c]);
             }
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
@@ -255,7 +268,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
 #pragma unroll
                     for (int c = 0; c < NRHS; ++c) {
                         if constexpr (STAGED) xv[u][c] = lds_x[col[u] * NRHS + c];
-                        else xv[u][c] = x[(int64_t)col[u] * NRHS + c];
+                        else xv[u][c] = ldx<T, COH>(&x_[(int64_t)col[u] * NRHS + c]);
                     }
                 }
 #pragma unroll
@@ -279,7 +292,10 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             for (int c = 0; c < NRHS; ++c) {
                 const T r = b[(int64_t)i * NRHS + c] - q[c];
                 if constexpr (RESID) rout[(int64_t)i * NRHS + c] = ((frozen >> c) & 1u) ? 0.0f : (float)r;
-                else if (!((frozen >> c) & 1u)) xn[(int64_t)i * NRHS + c] = xi[c] + di * r;
+                else if (!((frozen >> c) & 1u)) {
+                    if constexpr (COH) stx_dev(&xn_[(int64_t)i * NRHS + c], xi[c] + di * r);
+                    else xn[(int64_t)i * NRHS + c] = xi[c] + di * r;
+                }
                 const double rd = (double)r;
                 acc[c] = is_max ? maxnan(acc[c], fabs(rd)) : acc[c] + rd * rd;
             }
@@ -445,6 +461,35 @@ __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, co
             for (int c = 0; c < NRHS; ++c) part[(int64_t)tile * NRHS + c] = acc[c];
         }
     }
+}
+
+// Asynchronous (chaotic) relaxation: `rounds` passes over this workgroup's
+// tiles with no synchronisation between workgroups.  Each tile updates its
+// rows of x in place from whatever values of x it reads (its own staged
+// footprint, or direct gathers), so neighbouring tiles may see values of any
+// age; loads and stores of x are device-coherent, so every update becomes
+// visible to the other workgroups.  The stop test is left to the host, on
+// the quiescent x between launches.
+template <int NRHS, int CM>
+__global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds, int32_t lds_fp_bytes,
+                                              int32_t lds_runs)
+{
+    extern __shared__ __align__(16) char smem[];
+    double* lds_x = reinterpret_cast<double*>(smem);
+    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    int32_t* lds_ro = lds_rs + lds_runs;
+    const SysDev& S = *sys;
+    double* x = static_cast<double*>(S.x[0]);
+    int32_t first, end, stride;
+    xcd_items(S.ntiles, gridDim.x, blockIdx.x, first, end, stride);
+    for (int32_t r = 0; r < rounds; ++r)
+        for (int32_t tile = first; tile < end; tile += stride) {
+            double acc[NRHS];
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
+            sweep_tile<double, NRHS, CM, false, true>(S, tile, x, x, 0u, false, lds_x, lds_rs, lds_ro, acc);
+            if constexpr (CM == COL_LOCAL16) __syncthreads();    // the next tile restages the LDS
+        }
 }
 
 // Closing decisions of several systems (one workgroup each) on sweep k.
@@ -851,6 +896,33 @@ void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k)
     default: k_decide_multi<4><<<p.nsys, 256, 0, st>>>(p, k); break;
     }
     JAC_HIP(hipGetLastError());
+}
+
+template <int NRHS>
+void* async_cm(int colfmt)
+{
+    switch (colfmt) {
+    case COL_GLOBAL32: return reinterpret_cast<void*>(&k_async<NRHS, COL_GLOBAL32>);
+    case COL_REL16: return reinterpret_cast<void*>(&k_async<NRHS, COL_REL16>);
+    default: return reinterpret_cast<void*>(&k_async<NRHS, COL_LOCAL16>);
+    }
+}
+
+void* async_kernel(int nrhs, int colfmt)
+{
+    switch (nrhs) {
+    case 1: return async_cm<1>(colfmt);
+    case 2: return async_cm<2>(colfmt);
+    case 4: return async_cm<4>(colfmt);
+    default: fail(JAC_E_INVALID, "no asynchronous kernel for this right-hand-side count");
+    }
+}
+
+void launch_async(void* fn, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys, int rounds,
+                  int lds_fp_bytes, int lds_runs)
+{
+    void* args[] = {&sys, &rounds, &lds_fp_bytes, &lds_runs};
+    JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 
 void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k)

@@ -24,6 +24,10 @@ void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k);
 void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
                         const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs);
 void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k);
+// asynchronous relaxation: `rounds` in-place passes over the tiles, x = sys->x[0]
+void* async_kernel(int nrhs, int colfmt);
+void launch_async(void* fn, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys, int rounds,
+                  int lds_fp_bytes, int lds_runs);
 // mixed-precision refinement
 void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
                   float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs);
