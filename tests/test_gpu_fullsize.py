@@ -1,0 +1,104 @@
+"""GPU: parity at the full sizes the bench times.
+
+The 128^3 7-point Laplacian (n = 2,097,152, b = A x* as in the bench), 64
+parts under each split, the bench's default tile shape and loop:
+
+* one sweep from the device's own state x_k, checked on sampled rows (random
+  rows plus the first and last row of every part) against the oracle's
+  single-row sweep from the same x_k: the per-sweep bar, 1e-12 relative;
+* 2000 sweeps from x_0 = 0 against the oracle's 2000 sweeps.  The two sum
+  each row in a different rounding (fused multiply-add on the device, and the
+  substructured order permutes columns), so they drift apart by at most the
+  per-sweep rounding summed over the sweeps: a row of m = 7 entries differs
+  by at most about (m + 2) eps (|b_i| + sum_j |a_ij x_j|) / a_ii + eps |x_i|
+  per sweep, under 40 eps max(1, max|x|) here (|b_i| <= 12, |x| ~ 1), and
+  the Jacobi matrix has infinity norm 1, so after K sweeps the bound is
+  K * 50 eps max(1, max|x|);
+* the 192^3 control, whose band reaches past 16-bit row offsets (32-bit
+  columns), a few sweeps against the oracle under the same bound."""
+import numpy as np
+import pytest
+
+from gpu_util import B, get_x, make, need_gpu, sweep
+from oracle import ref
+from paper_2112_02377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+MODES = [(1, 64, None), (2, 64, None), (3, 64, (8, 8, 8))]
+_REF = {}
+
+
+@pytest.fixture(scope="module")
+def big():
+    return W.laplace7(128, workload=2)
+
+
+def ref_sweeps(s, K):
+    if K not in _REF:
+        _REF[K] = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K, threads=16)
+    return _REF[K]
+
+
+def sample_rows(s, h, rng):
+    got = B().jac_get_partition(h)
+    perm, bounds = got["perm"], got["bounds"]
+    edges = [int(perm[r]) for r in bounds[:-1] if r < s.n] + [int(perm[r - 1]) for r in bounds[1:] if r > 0]
+    return np.unique(np.concatenate([rng.choice(s.n, 4096, replace=False), edges, [0, s.n - 1]])).astype(np.int32)
+
+
+@pytest.mark.parametrize("mode,P,sub", MODES)
+def test_one_sweep_from_device_state_on_sampled_rows(big, mode, P, sub):
+    need_gpu()
+    b = B()
+    s = big
+    h = make(s, mode, P, sub)
+    sweep(h, 37)
+    xk = get_x(h, s.n)[0]
+    hist = sweep(h, 1)[:, 0]
+    xk1 = get_x(h, s.n)[0]
+    rows = sample_rows(s, h, np.random.default_rng(mode))
+    st, xr, _ = ref.sweep_rows(s.row_ptr, s.col_idx, s.vals, s.b[0], xk, rows)
+    assert st == ref.OK
+    scale = max(np.abs(xk1).max(), 1.0)
+    assert np.abs(xk1[rows] - xr).max() <= 1e-12 * scale
+    # the recorded norm is that of b - A x_k
+    r = np.linalg.norm(s.b[0] - s.scipy() @ xk)
+    assert abs(hist[0] - r) <= 1e-12 * r
+    b.jac_destroy(h)
+
+
+@pytest.mark.parametrize("mode,P,sub", MODES)
+def test_bench_sweeps_against_the_oracle(big, mode, P, sub):
+    need_gpu()
+    b = B()
+    s = big
+    K = 2000
+    _, xr, hr = ref_sweeps(s, K)
+    h = make(s, mode, P, sub)
+    hist = sweep(h, K)[:, 0]
+    x = get_x(h, s.n)[0]
+    bound = K * 50 * EPS * max(1.0, np.abs(xr).max())
+    assert np.abs(x - xr).max() <= bound
+    # norms: b - A x differs by at most ||A||_inf * bound per row
+    rn = np.sqrt(s.n) * 12 * bound
+    assert np.all(np.abs(hist - hr) <= 1e-12 * hr + rn)
+    b.jac_destroy(h)
+
+
+def test_192_control_uses_32_bit_columns():
+    need_gpu()
+    b = B()
+    s = W.laplace7(192, workload=2)
+    K = 6
+    h = make(s, 1, 64)
+    info = b.jac_get_info(h)
+    assert info["col_bytes"] == 4 and info["n"] == 7077888 and info["nnz"] == 49324032
+    hist = sweep(h, K)[:, 0]
+    x = get_x(h, s.n)[0]
+    b.jac_destroy(h)
+    _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K, threads=16)
+    bound = K * 50 * EPS * max(1.0, np.abs(xr).max())
+    assert np.abs(x - xr).max() <= bound
+    assert np.all(np.abs(hist - hr) <= 1e-12 * hr + np.sqrt(s.n) * 12 * bound)
