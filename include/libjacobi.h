@@ -193,13 +193,16 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double *hist_dev);
 jac_status jac_solve(jac_handle h, double tol, int32_t maxit, jac_norm norm, jac_prec prec,
                      int32_t *sweeps_out, double *relres_out);
 
-/* Solve nsys independent systems in one persistent launch (every system is
- * swept in lockstep; each (system, right-hand side) column stops on its own
- * relative 2-norm test and is frozen; a system with every column stopped
- * leaves the work list).  All handles must share the device and stream of
- * hs[0] and have their partition done; outputs are host arrays indexed
- * [s*4 + c] up to each handle's nrhs (stride 4).  Results equal nsys
- * separate jac_solve calls with JAC_NORM_L2_REL and JAC_FP64. */
+/* Solve nsys independent systems together: every system is swept in
+ * lockstep, one launch per global sweep over the tiles of the systems still
+ * running (default), or one persistent launch for the whole solve when
+ * hs[0] has JAC_OPT_LOOP = 1.  Each (system, right-hand side) column stops on
+ * its own relative 2-norm test and is frozen; a system with every column
+ * stopped leaves the work.  All handles must share the device and stream of
+ * hs[0], the right-hand-side count and the column format, and have their
+ * partition done; outputs are host arrays indexed [s*4 + c] up to each
+ * handle's nrhs (stride 4).  Results equal nsys separate jac_solve calls with
+ * JAC_NORM_L2_REL and JAC_FP64, bit for bit. */
 jac_status jac_solve_batched(const jac_handle *hs, int32_t nsys, double tol, int32_t maxit,
                              int32_t *sweeps_out_host, double *relres_out_host);
 
