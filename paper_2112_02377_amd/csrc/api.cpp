@@ -269,7 +269,7 @@ int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 {
     int nb = 0;
     JAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds));
-    if (nb < 1) fail(JAC_E_HIP, "persistent loop cannot be resident (LDS or registers too large)");
+    if (nb < 1) fail(JAC_E_HIP, "kernel cannot be resident (LDS or registers too large)");
     if (wg_per_cu > 0) nb = std::min(nb, wg_per_cu);
     int64_t g = (int64_t)nb * num_cus();
     g = std::min<int64_t>(g, std::max<int64_t>(work, 1));

@@ -42,22 +42,25 @@ struct SysState {
     int32_t done_k;           // system leaves the work list from this sweep on
     int32_t status;           // JAC_OK, JAC_NOT_CONVERGED, JAC_E_DIVERGED
     int32_t last_k;           // last sweep whose residual was reduced
-    uint32_t arrive;          // tiles finished in the current sweep
+    uint32_t pad_;
     double nrm[4];            // norms of the last reduced residual
 };
 
 // Sweep control.  One launch per sweep: the stop decision on the residual of
-// sweep k is taken by a dedicated workgroup of launch k+1 (or by the closing
-// reduction launch), so launches never synchronise inside a kernel; a third
-// iterate buffer keeps x_k intact while launch k+1 computes x_{k+2}
-// speculatively.  Persistent loop: the decision is taken by the workgroup that
-// finishes the last tile of a system, before the sweep's grid barrier.
+// sweep k is taken by a dedicated workgroup of launch k+1 (one per system
+// when several systems share the launch; or by the closing reduction
+// launch), so launches never synchronise inside a kernel; a third iterate
+// buffer keeps x_k intact while launch k+1 computes x_{k+2} speculatively.
+// Persistent loop: at the start of sweep k+1 (after the grid barrier that
+// ends sweep k) workgroup s mod G decides system s on sweep k, and the
+// decision takes effect two sweeps later, so every workgroup reads the same
+// work list.
 struct LoopParams {
     const SysDev* sys;        // [nsys]
     SysState* st;             // [nsys]
     const int32_t* tile_base; // [nsys+1] prefix of tile counts (static)
     double* hist;             // nullable, [(k - k0) * nrhs + c] of system 0
-    uint32_t* bar;            // [2] grid barrier: count, generation
+    uint32_t* bar;            // persistent loop's grid barrier (group counters, top, generation)
     int32_t nsys;
     int32_t k0;               // first sweep
     int32_t kend;             // fixed mode: sweeps k0..kend-1; solve mode: test up to kend (maxit)

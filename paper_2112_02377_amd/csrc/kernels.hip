@@ -15,9 +15,11 @@
 //
 // The norm (section 3 algorithm; section 4.2.3, local sums combined by an
 // all-reduce) is reduced deterministically: fixed shuffle tree in a wave,
-// fixed wave order in a workgroup, one partial per tile, and the last tile
-// of a system to finish sums the tile partials in tile order.  No floating
-// point atomics are used anywhere, so reruns are bit-identical.
+// fixed wave order in a workgroup, one partial per tile, and a deciding
+// workgroup sums a sweep's tile partials in tile order (the extra workgroup
+// of the next launch, or in the persistent loop workgroup s mod G of the next
+// sweep).  No floating point atomics are used anywhere, so reruns are
+// bit-identical.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -765,7 +767,7 @@ __global__ void k_init_state(SysState* st, int32_t nsys, int32_t nrhs_unused)
         st[s].done_k = kRunning;
         st[s].status = JAC_OK;
         st[s].last_k = -1;
-        st[s].arrive = 0;
+        st[s].pad_ = 0;
     }
     (void)nrhs_unused;
 }
