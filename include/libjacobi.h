@@ -169,6 +169,16 @@ jac_status jac_partition(jac_handle h, jac_mode mode, int32_t nparts, const int3
 jac_status jac_get_partition(jac_handle h, int32_t *perm_host, int32_t *bounds_host, int32_t *nbounds,
                              int32_t *recv_ptr_host, int32_t *recv_idx_host, int64_t *nrecv);
 
+/* Send lists of the split: the transpose of the receive lists (the sending
+ * dependency table of section 4.2.2; for substructuring, the interface
+ * values each part provides).  send_ptr[nparts+1]: part q sends entries
+ * [send_ptr[q], send_ptr[q+1]) of send_dest (destination part) and send_idx
+ * (row, new numbering), ordered by destination, then row.  On entry *nsend
+ * gives the capacity of send_dest and send_idx (ignored when both are NULL);
+ * on return it holds the size.  Any output may be NULL; host arrays. */
+jac_status jac_get_send_lists(jac_handle h, int32_t *send_ptr_host, int32_t *send_dest_host, int32_t *send_idx_host,
+                              int64_t *nsend);
+
 /* Set x (n x nrhs, original order, device) or zero it (x_dev = NULL). */
 jac_status jac_set_x(jac_handle h, const double *x_dev);
 

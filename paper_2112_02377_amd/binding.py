@@ -30,7 +30,7 @@ PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
            "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
-           "jac_graph_partition", "jac_solve_async"]
+           "jac_graph_partition", "jac_solve_async", "jac_get_send_lists"]
 
 
 class jac_info(C.Structure):
@@ -84,6 +84,7 @@ def lib():
             "jac_get_info": [_vp, C.POINTER(jac_info)],
             "jac_graph_partition": [C.c_int32, _i32p, _i32p, C.c_int32, _i32p],
             "jac_solve_async": [_vp, C.c_double, C.c_int32, C.c_int, C.c_int32, _i32p, _f64p],
+            "jac_get_send_lists": [_vp, _i32p, _i32p, _i32p, _i64p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -187,6 +188,20 @@ def jac_get_partition(h):
     _check(L.jac_get_partition(h, perm.ctypes.data_as(_i32p), bounds.ctypes.data_as(_i32p), C.byref(nb),
                                rptr.ctypes.data_as(_i32p), ridx.ctypes.data_as(_i32p), C.byref(nr)))
     return dict(perm=perm, bounds=bounds[:nb.value], recv_ptr=rptr, recv_idx=ridx[:nr.value])
+
+
+def jac_get_send_lists(h):
+    """Returns dict(send_ptr, send_dest, send_idx) as numpy arrays."""
+    L = lib()
+    ns = C.c_int64(0)
+    _check(L.jac_get_send_lists(h, None, None, None, C.byref(ns)))
+    P = jac_get_info(h)["nparts"]
+    sptr = np.zeros(P + 1, np.int32)
+    dest = np.zeros(max(ns.value, 1), np.int32)
+    idx = np.zeros(max(ns.value, 1), np.int32)
+    _check(L.jac_get_send_lists(h, sptr.ctypes.data_as(_i32p), dest.ctypes.data_as(_i32p), idx.ctypes.data_as(_i32p),
+                                C.byref(ns)))
+    return dict(send_ptr=sptr, send_dest=dest[:ns.value], send_idx=idx[:ns.value])
 
 
 def jac_set_x(h, x_dev=None):

@@ -575,6 +575,40 @@ jac_status jac_get_partition(jac_handle h, int32_t* perm, int32_t* bounds, int32
     });
 }
 
+jac_status jac_get_send_lists(jac_handle h, int32_t* send_ptr, int32_t* send_dest, int32_t* send_idx, int64_t* nsend)
+{
+    return guarded([&]() -> jac_status {
+        if (!h) fail(JAC_E_INVALID, "NULL handle");
+        const Partition& p = h->part;
+        const int32_t P = p.nparts;
+        const size_t m = p.recv_idx.size();
+        if ((send_dest || send_idx) && (!nsend || *nsend < (int64_t)m)) fail(JAC_E_INVALID, "send arrays too small");
+        // transpose of the receive lists: (owner, destination, row), sorted
+        struct E { int32_t src, dst, row; };
+        std::vector<E> e;
+        e.reserve(m);
+        for (int32_t q = 0; q < P; ++q)
+            for (int32_t t = p.recv_ptr[q]; t < p.recv_ptr[q + 1]; ++t)
+                e.push_back({p.owner[p.recv_idx[t]], q, p.recv_idx[t]});
+        std::sort(e.begin(), e.end(), [](const E& a, const E& b) {
+            if (a.src != b.src) return a.src < b.src;
+            if (a.dst != b.dst) return a.dst < b.dst;
+            return a.row < b.row;
+        });
+        if (send_ptr) {
+            std::fill(send_ptr, send_ptr + P + 1, 0);
+            for (const E& x : e) send_ptr[x.src + 1]++;
+            for (int32_t q = 0; q < P; ++q) send_ptr[q + 1] += send_ptr[q];
+        }
+        for (size_t t = 0; t < m; ++t) {
+            if (send_dest) send_dest[t] = e[t].dst;
+            if (send_idx) send_idx[t] = e[t].row;
+        }
+        if (nsend) *nsend = (int64_t)m;
+        return JAC_OK;
+    });
+}
+
 jac_status jac_set_x(jac_handle h, const double* x_dev)
 {
     return guarded([&]() -> jac_status {

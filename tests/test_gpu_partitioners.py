@@ -81,3 +81,61 @@ def torch_sweeps(h, K):
     from gpu_util import sweep
     B().jac_set_x(h, None)
     return sweep(h, K)[:, 0]
+
+
+def test_send_lists_reproduce_the_papers_tables():
+    # the 10-row, three-band example of section 4.2.2: the library's receive
+    # and send lists are the paper's receiving and sending dependency tables
+    need_gpu()
+    from test_oracle_partition import tab_dep
+    b = B()
+    rp, ci, P, recv, send = tab_dep()
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    vals = np.where(ci == rows, 10.0, -1.0)
+    h = b.jac_create(n, rp, ci, vals, 1, np.ones(n))
+    b.jac_partition(h, b.JAC_BANDROW_SP, P)
+    got = b.jac_get_partition(h)
+    bounds = got["bounds"]
+    owner = np.searchsorted(bounds, np.arange(n), side="right") - 1
+    r = {}
+    for p in range(P):
+        for i in got["recv_idx"][got["recv_ptr"][p]:got["recv_ptr"][p + 1]]:
+            r.setdefault((p, int(owner[i])), []).append(int(i))
+    assert r == recv
+    sl = b.jac_get_send_lists(h)
+    s = {}
+    for q in range(P):
+        for d, i in zip(sl["send_dest"][sl["send_ptr"][q]:sl["send_ptr"][q + 1]],
+                        sl["send_idx"][sl["send_ptr"][q]:sl["send_ptr"][q + 1]]):
+            s.setdefault((q, int(d)), []).append(int(i))
+    assert s == send
+    b.jac_destroy(h)
+
+
+@pytest.mark.parametrize("mode,partitioner,P,sub", [(2, 0, 7, None), (3, 0, 8, (2, 2, 2)), (2, 2, 6, None),
+                                                    (3, 2, 4, (3, 2, 1))])
+def test_send_lists_are_the_transpose_of_the_receive_lists(mode, partitioner, P, sub):
+    need_gpu()
+    b = B()
+    s = W.laplace7(14, workload=1)
+    h = make(s, opts={b.JAC_OPT_PARTITIONER: partitioner})
+    b.jac_partition(h, mode, P, sub)
+    got = b.jac_get_partition(h)
+    bounds = got["bounds"]
+    if mode == 3:
+        S = int(np.prod(sub))
+        sub_int, sub_ifc, part_sub = bounds[:S + 1], bounds[S + 1:2 * S + 2], bounds[2 * S + 2:]
+        owner = np.zeros(s.n, dtype=np.int64)
+        for q in range(P):
+            for t in range(part_sub[q], part_sub[q + 1]):
+                owner[sub_int[t]:sub_int[t + 1]] = q
+                owner[sub_ifc[t]:sub_ifc[t + 1]] = q
+    else:
+        owner = np.searchsorted(bounds, np.arange(s.n), side="right") - 1
+    sptr, sdest, sidx = OP.send_lists(got["recv_ptr"], got["recv_idx"], owner, P)
+    sl = b.jac_get_send_lists(h)
+    assert np.array_equal(sl["send_ptr"], sptr)
+    assert np.array_equal(sl["send_dest"], sdest) and np.array_equal(sl["send_idx"], sidx)
+    assert sl["send_ptr"][-1] == got["recv_ptr"][-1]
+    b.jac_destroy(h)
