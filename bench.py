@@ -121,8 +121,9 @@ def secondary(B, W, torch, stream, with_oracle=True):
     the adjoint (64^3 diffusion, K = 400, checkpoint every 20) against its
     forward sweeps; then the Q1 FE stand-ins of the paper's Set-1 cubes solved
     with its stop test, beside its iteration counts and CPU-cluster times, the
-    weighted partitioners against equal-row bands, and the asynchronous
-    relaxation against the synchronous solve.
+    weighted partitioners against equal-row bands, the asynchronous
+    relaxation against the synchronous solve, and the control configurations
+    (20^3 solves, 128^3 with 4x4x4 subdomains, 192^3).
     Times are HIP-event times on the handles' stream."""
     import numpy as np
     out = {}
@@ -215,7 +216,51 @@ def secondary(B, W, torch, stream, with_oracle=True):
     out["partitions"] = partitions(B, W, torch, stream)
     # -- asynchronous relaxation against the synchronous solve
     out["async"] = async_vs_sync(B, W, torch, stream)
+    # -- the small configuration's solves and the 128^3 / 192^3 controls
+    out["controls"] = controls(B, W, torch, stream)
     return out
+
+
+def controls(B, W, torch, stream):
+    """The 20^3 Laplacian solved to relative 1e-8 under each split (4 parts;
+    substructuring on 2x2x1 blocks), the 128^3 substructuring with one
+    subdomain per part (4x4x4 subdomains of 32^3, 64 parts), and the 192^3
+    band-row control (its band needs 32-bit column offsets)."""
+    sc = stream.cuda_stream
+    res = {}
+    s = W.laplace7(20, workload=1)
+    h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+    B.jac_set_grid(h, 20, 20, 20)
+    c1 = {}
+    for name, mode, sub in (("JB", B.JAC_BANDROW, None), ("JBO", B.JAC_BANDROW_SP, None),
+                            ("JSS", B.JAC_SUBSTRUCT, (2, 2, 1))):
+        B.jac_partition(h, mode, 4, sub)
+        B.jac_set_x(h, None)
+        B.jac_solve(h, 1e-8, 5000)
+        B.jac_set_x(h, None)
+        ms, (st, sw, rr) = _timed(torch, stream, lambda: B.jac_solve(h, 1e-8, 5000))
+        c1[name] = {"sweeps": int(sw[0]), "ms": round(ms, 3), "relres": float(rr[0]),
+                    "sweeps_per_s": round(int(sw[0]) / (ms / 1e3), 1)}
+    B.jac_destroy(h)
+    res["laplace7_20_solve"] = c1
+    for name, N, mode, P, sub, K in (("laplace7_128_jss_4x4x4", 128, B.JAC_SUBSTRUCT, 64, (4, 4, 4), 500),
+                                     ("laplace7_192_jb", 192, B.JAC_BANDROW, 64, None, 200)):
+        s = W.laplace7(N, workload=2)
+        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
+        B.jac_set_grid(h, N, N, N)
+        B.jac_partition(h, mode, P, sub)
+        B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
+        B.jac_set_x(h, None)
+        B.jac_sweep(h, 20)
+        B.jac_sweep(h, K)
+        info = B.jac_get_info(h)
+        us = info["last_loop_ms"] * 1e3 / K
+        res[name] = {"us_per_sweep": round(us, 3), "GBps": round(info["alg_bytes_per_sweep"] / us / 1e3, 1),
+                     "pct_hbm_peak": round(100 * info["alg_bytes_per_sweep"] / us / 1e3 / HBM_PEAK_GBS, 2),
+                     "halo_entries": int(info["halo_entries"]), "col_bytes": int(info["col_bytes"]), "n": s.n,
+                     "nnz": s.nnz}
+        B.jac_destroy(h)
+    return res
 
 
 def async_vs_sync(B, W, torch, stream):
@@ -420,7 +465,8 @@ def main():
         avg = sum(loop_ms[m]) / len(loop_ms[m])
         gbs = alg[m] * K / (avg / 1e3) / 1e9
         i = infos[m]
-        per_mode[m] = {"loop_ms": round(avg, 3), "us_per_sweep": round(avg * 1e3 / K, 3),
+        med = sorted(loop_ms[m])[len(loop_ms[m]) // 2]
+        per_mode[m] = {"loop_ms": round(avg, 3), "loop_ms_median": round(med, 3), "us_per_sweep": round(avg * 1e3 / K, 3),
                        "sweeps_per_s": round(K / (avg / 1e3), 1), "GBps": round(gbs, 1),
                        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
                        "dev_GBps": round(i["dev_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
