@@ -96,7 +96,7 @@ using namespace jac;
 extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const double* gx_dev, double* gb_dev,
                                   double* gvals_dev)
 {
-    try {
+    return guarded([&]() -> jac_status {
         if (!hp || !gx_dev) fail(JAC_E_INVALID, "NULL argument");
         Handle& h = *hp;
         if (K < 0 || ckpt < 1) fail(JAC_E_INVALID, "need K >= 0 and ckpt_every >= 1");
@@ -239,11 +239,5 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                                nnz, gvals_dev, st);
         h.sync();
         return JAC_OK;
-    } catch (const Error& e) {
-        set_last_error(e.msg);
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        set_last_error("host allocation failed");
-        return JAC_E_NOMEM;
-    }
+    });
 }

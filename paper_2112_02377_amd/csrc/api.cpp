@@ -32,23 +32,6 @@ void hip_check(hipError_t e, const char* what)
 
 void set_last_error(const std::string& m) { g_last_error = m; }
 
-template <typename F>
-static jac_status guarded(F&& f)
-{
-    try {
-        return f();
-    } catch (const Error& e) {
-        g_last_error = e.msg;
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return JAC_E_NOMEM;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return JAC_E_INVALID;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------

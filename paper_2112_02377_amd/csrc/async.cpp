@@ -25,7 +25,7 @@ using namespace jac;
 extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, jac_norm norm,
                                       int32_t rounds_per_check, int32_t* rounds_out, double* relres_out)
 {
-    try {
+    return guarded([&]() -> jac_status {
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
         if (!(tol >= 0.0) || maxit < 0) fail(JAC_E_INVALID, "tol must be >= 0 and maxit >= 0");
         if (norm != JAC_NORM_L2_REL && norm != JAC_NORM_INF_ABS) fail(JAC_E_INVALID, "bad norm");
@@ -102,11 +102,5 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
         }
         if (status == JAC_E_DIVERGED) fail(JAC_E_DIVERGED, "residual norm diverged in the asynchronous solve");
         return (jac_status)status;
-    } catch (const Error& e) {
-        set_last_error(e.msg);
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        set_last_error("host allocation failed");
-        return JAC_E_NOMEM;
-    }
+    });
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -108,6 +110,25 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
               int fp_bytes, int runs, int colfmt, int nrhs);
 jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t* sweeps_out, double* relres_out);
 void set_last_error(const std::string& m);
+
+// Runs the body of an ABI entry point: every exception becomes a status and
+// the thread's last-error message, so none crosses the C boundary.
+template <typename F>
+jac_status guarded(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return JAC_E_NOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return JAC_E_INVALID;
+    }
+}
 
 }  // namespace jac
 

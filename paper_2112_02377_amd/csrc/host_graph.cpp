@@ -451,7 +451,7 @@ using namespace jac;
 extern "C" jac_status jac_graph_partition(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t nparts,
                                           int32_t* part_out)
 {
-    try {
+    return guarded([&]() -> jac_status {
         if (n < 1 || !row_ptr || !col_idx || !part_out) fail(JAC_E_INVALID, "NULL argument or n < 1");
         if (row_ptr[0] != 0) fail(JAC_E_INVALID, "row_ptr[0] must be 0");
         Csr a;
@@ -466,11 +466,5 @@ extern "C" jac_status jac_graph_partition(int32_t n, const int32_t* row_ptr, con
         graph_partition(a, nparts, part);
         std::copy(part.begin(), part.end(), part_out);
         return JAC_OK;
-    } catch (const Error& e) {
-        set_last_error(e.msg);
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        set_last_error("host allocation failed");
-        return JAC_E_NOMEM;
-    }
+    });
 }

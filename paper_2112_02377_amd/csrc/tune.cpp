@@ -85,7 +85,7 @@ using namespace jac;
 
 extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
 {
-    try {
+    return guarded([&]() -> jac_status {
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
         if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
         Handle& h = *hp;
@@ -128,11 +128,5 @@ extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
         h.sync();
         cache_store(key, pick.tile_rows, pick.block, best * 1e3 / sweeps_per_trial);
         return JAC_OK;
-    } catch (const Error& e) {
-        set_last_error(e.msg);
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        set_last_error("host allocation failed");
-        return JAC_E_NOMEM;
-    }
+    });
 }
