@@ -166,31 +166,46 @@ def secondary(B, W, torch, stream, with_oracle=True):
     # -- batched
     systems = W.diffusion_batch(256, workload=4)
     hs = [B.jac_create(x.n, x.row_ptr, x.col_idx, x.vals, 4, x.b.reshape(-1), stream=sc) for x in systems]
-    # persistent launch first, then the default (one launch per global sweep)
+    # 256 separate solves and the batched solve, both on the default tile
+    # shape (identical arithmetic: equal sweep counts)
+    def seq():
+        return [B.jac_solve(hh, 1e-8, 1000000) for hh in hs]
+    ms_s, rs = _timed(torch, stream, seq)
+    for hh in hs:
+        B.jac_set_x(hh, None)
+    ms_d, (st, swd, rrd) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
+    same = all(int((swd[i, :4] != r[1]).sum()) == 0 for i, r in enumerate(rs))
+    # then one tile shape for the whole batch from the batched autotuner
+    # (not timed), persistent launch, and the default one launch per sweep
+    for hh in hs:
+        B.jac_set_x(hh, None)
+    t0 = time.perf_counter()
+    B.jac_autotune_batched(hs, 32)
+    t_tune = time.perf_counter() - t0
+    shape = (B.jac_get_option(hs[0], B.JAC_OPT_TILE_ROWS), B.jac_get_option(hs[0], B.JAC_OPT_BLOCK))
     B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 1)
     ms_p, (st, swp, rrp) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
     B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 0)
     for hh in hs:
         B.jac_set_x(hh, None)
     ms_b, (st, swb, rrb) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
-    for hh in hs:
-        B.jac_set_x(hh, None)
-
-    def seq():
-        return [B.jac_solve(hh, 1e-8, 1000000) for hh in hs]
-    ms_s, rs = _timed(torch, stream, seq)
-    same = all(int((swb[i, :4] != r[1]).sum()) == 0 for i, r in enumerate(rs))
     alg = 0
     for x, k in zip(systems, swb):
         alg += (12 * x.nnz + 4 * (x.n + 1) + 8 * x.n + 96 * x.n) * (int(k[:4].max()) + 1)
     out["batched"] = {
         "workload": f"256 diffusion systems, edges U[16,64], n total {sum(x.n for x in systems)}, 4 rhs, tol 1e-8",
         "batched_ms": round(ms_b, 3), "persistent_ms": round(ms_p, 3), "sequential_ms": round(ms_s, 3),
+        "batched_default_tiles_ms": round(ms_d, 3),
         "speedup_vs_sequential": round(ms_s / ms_b, 3), "max_sweeps": int(swb[:, :4].max()),
         "sum_system_sweeps": int(swb[:, :4].max(axis=1).sum()),
         "batched_alg_GBps": round(alg / ms_b / 1e6, 1), "persistent_alg_GBps": round(alg / ms_p / 1e6, 1),
         "sequential_alg_GBps": round(alg / ms_s / 1e6, 1),
-        "sweep_counts_equal": bool(same and np.array_equal(swb, swp))}
+        "sweep_counts_equal_to_separate_solves": bool(same),
+        "tuned_vs_default_max_sweep_diff": int(np.abs(swb[:, :4] - swd[:, :4]).max()),
+        "persistent_equals_per_sweep_launches": bool(np.array_equal(swb, swp)),
+        "tuned_tile_rows": int(shape[0]), "tuned_block": int(shape[1]), "tune_s": round(t_tune, 2),
+        "note": "separate solves use the default tile shape (512 rows), the tuned batch the shape "
+                "jac_autotune_batched picked for the batch"}
     for hh in hs:
         B.jac_destroy(hh)
     # -- adjoint

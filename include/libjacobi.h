@@ -249,6 +249,14 @@ jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double
  * $JAC_TUNE_CACHE (if set), keyed by the matrix shape and split. */
 jac_status jac_autotune(jac_handle h, int32_t sweeps_per_trial);
 
+/* Tile shape for a batch (jac_solve_batched): times sweeps_per_trial
+ * lockstep sweeps of the whole batch for each candidate shape (every system
+ * re-planned to it) and keeps the fastest for all systems; every system's x
+ * is restored.  A system alone may prefer small tiles that fill the chip,
+ * which in a batch the other systems already do, so the shape is timed on
+ * the batch.  Cached under $JAC_TUNE_CACHE like jac_autotune. */
+jac_status jac_autotune_batched(const jac_handle *hs, int32_t nsys, int32_t sweeps_per_trial);
+
 /* Host only (no device, no handle): split the graph of a sparse pattern into
  * nparts parts of about equal weight with few cut edges -- the partition the
  * paper proposes for load-balanced band rows (section 4.2.2: vertex i weighs

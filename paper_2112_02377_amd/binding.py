@@ -30,7 +30,7 @@ PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
            "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
-           "jac_graph_partition", "jac_solve_async", "jac_get_send_lists"]
+           "jac_graph_partition", "jac_solve_async", "jac_get_send_lists", "jac_autotune_batched"]
 
 
 class jac_info(C.Structure):
@@ -85,6 +85,7 @@ def lib():
             "jac_graph_partition": [C.c_int32, _i32p, _i32p, C.c_int32, _i32p],
             "jac_solve_async": [_vp, C.c_double, C.c_int32, C.c_int, C.c_int32, _i32p, _f64p],
             "jac_get_send_lists": [_vp, _i32p, _i32p, _i32p, _i64p],
+            "jac_autotune_batched": [C.POINTER(_vp), C.c_int32, C.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -257,6 +258,11 @@ def jac_adjoint(h, K, ckpt_every, gx_dev, gb_dev=None, gvals_dev=None):
 
 def jac_autotune(h, sweeps_per_trial=20):
     return _check(lib().jac_autotune(h, int(sweeps_per_trial)))
+
+
+def jac_autotune_batched(handles, sweeps_per_trial=32):
+    arr = (_vp * len(handles))(*[h.value if isinstance(h, _vp) else h for h in handles])
+    return _check(lib().jac_autotune_batched(arr, len(handles), int(sweeps_per_trial)))
 
 
 def jac_graph_partition(row_ptr, col_idx, nparts):

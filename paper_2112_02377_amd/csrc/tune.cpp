@@ -130,3 +130,81 @@ extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
         return JAC_OK;
     });
 }
+
+// Batched solve: one tile shape for the whole batch, timed on the batch
+// itself (a system alone may prefer smaller tiles that fill the chip, while
+// in the batch the other systems already do).
+extern "C" jac_status jac_autotune_batched(const jac_handle* hs, int32_t nsys, int32_t sweeps_per_trial)
+{
+    return guarded([&]() -> jac_status {
+        if (!hs || nsys < 1) fail(JAC_E_INVALID, "need at least one handle");
+        if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
+        for (int32_t s = 0; s < nsys; ++s)
+            if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
+        static const Cand kBatch[] = {{256, 256}, {512, 256}, {1024, 256}, {2048, 256}};
+        Handle& h0 = *hs[0];
+        int64_t sum_n = 0, sum_nnz = 0;
+        for (int32_t s = 0; s < nsys; ++s) {
+            sum_n += hs[s]->a.n;
+            sum_nnz += hs[s]->a.nnz();
+        }
+        std::ostringstream k;
+        k << "batch " << nsys << ' ' << sum_n << ' ' << sum_nnz << ' ' << h0.nrhs << ' ' << h0.part_mode << ' '
+          << h0.part_nparts;
+        const std::string key = k.str();
+        auto apply = [&](int32_t rows, int32_t block) {
+            for (int32_t s = 0; s < nsys; ++s) {
+                Handle& h = *hs[s];
+                h.opt.block = block;
+                if (h.opt.tile_rows != rows) {
+                    h.opt.tile_rows = rows;
+                    h.replan(h.part_mode, h.part_nparts, h.part_has_sub ? h.part_sub : nullptr);
+                }
+            }
+        };
+        int32_t rows = 0, block = 0;
+        if (cache_lookup(key, rows, block)) {
+            apply(rows, block);            // re-planning keeps every system's x
+            return JAC_OK;
+        }
+        // keep every system's iterate across the trials
+        std::vector<DevMem> xs((size_t)nsys);
+        for (int32_t s = 0; s < nsys; ++s) {
+            xs[s].alloc((size_t)hs[s]->a.n * hs[s]->nrhs * sizeof(double));
+            hs[s]->get_x_dev(static_cast<double*>(xs[s].p));
+        }
+        auto restore = [&]() {
+            for (int32_t s = 0; s < nsys; ++s) {
+                Handle& h = *hs[s];
+                launch_gather_in(static_cast<const double*>(xs[s].p), static_cast<const int32_t*>(h.d.perm.p), h.a.n,
+                                 h.nrhs, static_cast<double*>(h.d.x0.p), h.stream);
+            }
+        };
+        for (auto& e : h0.ev)
+            if (!e) JAC_HIP(hipEventCreate(&e));
+        double best = 1e300;
+        Cand pick = {h0.opt.tile_rows, h0.opt.block};
+        for (const Cand& c : kBatch) {
+            apply(c.tile_rows, c.block);
+            restore();
+            for (int32_t s = 0; s < nsys; ++s) hs[s]->sync();
+            JAC_HIP(hipEventRecord(h0.ev[0], h0.stream));
+            // tolerance 0: every column runs the trial's sweeps
+            const jac_status st = jac_solve_batched(hs, nsys, 0.0, sweeps_per_trial, nullptr, nullptr);
+            if (st < 0) fail(st, "batched trial failed");
+            JAC_HIP(hipEventRecord(h0.ev[1], h0.stream));
+            JAC_HIP(hipEventSynchronize(h0.ev[1]));
+            float ms = 0.f;
+            JAC_HIP(hipEventElapsedTime(&ms, h0.ev[0], h0.ev[1]));
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        apply(pick.tile_rows, pick.block);
+        restore();
+        for (int32_t s = 0; s < nsys; ++s) hs[s]->sync();
+        cache_store(key, pick.tile_rows, pick.block, best * 1e3 / sweeps_per_trial);
+        return JAC_OK;
+    });
+}

@@ -41,3 +41,32 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     assert b.jac_get_option(h2, b.JAC_OPT_TILE_ROWS) == rows and b.jac_get_option(h2, b.JAC_OPT_BLOCK) == block
     assert len(cache.read_text().splitlines()) == 1
     b.jac_destroy(h2)
+
+
+def test_autotune_batched_keeps_state_and_results(tmp_path, monkeypatch):
+    need_gpu()
+    b = B()
+    cache = tmp_path / "tune_batch.txt"
+    monkeypatch.setenv("JAC_TUNE_CACHE", str(cache))
+    systems = W.diffusion_batch(6, workload=4, lo=6, hi=20)
+    hs = [make(s, 1, 1) for s in systems]
+    rng = np.random.default_rng(9)
+    x0 = [rng.uniform(-1, 1, s.n * 4) for s in systems]
+    for h, x in zip(hs, x0):
+        set_x(h, x)
+    b.jac_autotune_batched(hs, 8)
+    shapes = {(b.jac_get_option(h, b.JAC_OPT_TILE_ROWS), b.jac_get_option(h, b.JAC_OPT_BLOCK)) for h in hs}
+    assert len(shapes) == 1 and shapes.pop() in {(256, 256), (512, 256), (1024, 256), (2048, 256)}
+    for h, s, x in zip(hs, systems, x0):
+        assert np.array_equal(get_x(h, s.n, 4).reshape(-1), x)         # iterates restored
+        set_x(h, np.zeros(s.n * 4))
+    st, sw, rr = b.jac_solve_batched(hs, 1e-8, 100000)
+    assert st == b.JAC_OK
+    for si, (h, s) in enumerate(zip(hs, systems)):
+        xb = get_x(h, s.n, 4)
+        set_x(h, np.zeros(s.n * 4))
+        st1, sw1, rr1 = b.jac_solve(h, 1e-8, 100000)
+        assert np.array_equal(sw[si], sw1) and np.array_equal(xb, get_x(h, s.n, 4))
+    assert len(cache.read_text().splitlines()) == 1 and cache.read_text().startswith("batch 6 ")
+    for h in hs:
+        b.jac_destroy(h)
