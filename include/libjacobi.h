@@ -113,6 +113,8 @@ typedef struct {
     double last_loop_ms;         /* duration of the last sweep loop (JAC_OPT_TIMING) */
     int32_t last_loop_sweeps;    /* sweeps that loop ran (incl. a final test sweep)  */
     int32_t pad_;
+    int64_t state_gen;           /* raised by every call that changes the system, its
+                                    split or x (checkpoints stay valid while it holds) */
 } jac_info;
 
 /* Create a system from host CSR arrays (row_ptr[n+1], col_idx[nnz],
@@ -233,11 +235,21 @@ jac_status jac_solve_batched(const jac_handle *hs, int32_t nsys, double tol, int
 jac_status jac_solve_async(jac_handle h, double tol, int32_t maxit, jac_norm norm, int32_t rounds_per_check,
                            int32_t *rounds_out, double *relres_out);
 
+/* K sweeps from x_0 = 0 for right-hand side 0 (like jac_set_x(NULL) then
+ * jac_sweep(K)), keeping the iterates x_{j*ckpt_every} on the device as the
+ * checkpoints of a later jac_adjoint with the same K and stride, which then
+ * skips its own forward pass.  The checkpoints stay valid until a call
+ * changes the system, its split or x (jac_info.state_gen).  Leaves x_K in the
+ * handle. */
+jac_status jac_sweep_checkpointed(jac_handle h, int32_t K, int32_t ckpt_every);
+
 /* Reverse-mode derivative of K sweeps from x_0 = 0 for right-hand side 0:
  * given gx_dev = dL/dx_K (n, original order), writes gb_dev = dL/db (n) and
  * gvals_dev = dL/dvals (nnz, caller's CSR entry order, diagonal included).
  * Iterates are checkpointed every ckpt_every sweeps and recomputed per
- * segment.  Leaves x = x_K in the handle.  Either output may be NULL.
+ * segment; the forward pass that takes the checkpoints is skipped when
+ * jac_sweep_checkpointed left valid ones for this K and stride.  Leaves
+ * x = x_K in the handle.  Either output may be NULL.
  * Device memory: ceil(K/ckpt_every) + 2*ckpt_every + 5 vectors of n doubles plus
  * one double per stored slot (at most JAC_OPT_CKPT_MEM_MB, else
  * JAC_E_INVALID), kept by the handle for later calls until jac_destroy. */

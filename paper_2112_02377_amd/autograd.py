@@ -2,9 +2,11 @@
 
 ``JacobiK.apply(vals, b, handle, K, ckpt_every)`` returns x_K, the iterate
 after K synchronous Jacobi sweeps from x_0 = 0 on A(vals) x = b, where
-``vals`` are the matrix coefficients in the handle's CSR entry order.  Its
-backward calls ``jac_adjoint`` (checkpointed reverse sweeps on the device) and
-returns dL/dvals and dL/db.  Any differentiable torch expression producing
+``vals`` are the matrix coefficients in the handle's CSR entry order.  The
+forward keeps its checkpoints on the device (``jac_sweep_checkpointed``); the
+backward calls ``jac_adjoint`` (checkpointed reverse sweeps on the device),
+which reuses them when the handle was not touched in between, and returns
+dL/dvals and dL/db.  Any differentiable torch expression producing
 ``vals`` (for instance ``diffusion_values`` below) then carries the gradient
 on to its own parameters.
 
@@ -26,20 +28,22 @@ class JacobiK(torch.autograd.Function):
         b = b.detach().contiguous()
         B.jac_set_values(handle, vals)
         B.jac_set_rhs(handle, b)
-        B.jac_set_x(handle, None)
-        B.jac_sweep(handle, int(K))
+        B.jac_sweep_checkpointed(handle, int(K), int(ckpt_every))
         x = torch.empty_like(b)
         B.jac_get_x(handle, x)
         ctx.save_for_backward(vals, b)
         ctx.handle, ctx.K, ctx.ckpt = handle, int(K), int(ckpt_every)
+        ctx.state = B.jac_get_info(handle)["state_gen"]
         return x
 
     @staticmethod
     def backward(ctx, gx):
         vals, b = ctx.saved_tensors
-        # the handle may have been used since the forward: restore its system
-        B.jac_set_values(ctx.handle, vals)
-        B.jac_set_rhs(ctx.handle, b)
+        # if the handle was used since the forward, restore its system (the
+        # adjoint then takes its checkpoints again)
+        if B.jac_get_info(ctx.handle)["state_gen"] != ctx.state:
+            B.jac_set_values(ctx.handle, vals)
+            B.jac_set_rhs(ctx.handle, b)
         gb = torch.empty_like(b)
         gv = torch.empty_like(vals)
         B.jac_adjoint(ctx.handle, ctx.K, ctx.ckpt, gx.contiguous(), gb, gv)

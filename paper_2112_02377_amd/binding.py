@@ -30,7 +30,8 @@ PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_partition", "jac_get_partition",
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
            "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
-           "jac_graph_partition", "jac_solve_async", "jac_get_send_lists", "jac_autotune_batched"]
+           "jac_graph_partition", "jac_solve_async", "jac_get_send_lists", "jac_autotune_batched",
+           "jac_sweep_checkpointed"]
 
 
 class jac_info(C.Structure):
@@ -39,7 +40,8 @@ class jac_info(C.Structure):
                 ("max_footprint", C.c_int32), ("col_bytes", C.c_int32), ("halo_entries", C.c_int64),
                 ("staged_entries", C.c_int64), ("alg_bytes_per_sweep", C.c_int64),
                 ("dev_bytes_per_sweep", C.c_int64), ("loop_grid", C.c_int32), ("block", C.c_int32),
-                ("last_loop_ms", C.c_double), ("last_loop_sweeps", C.c_int32), ("pad_", C.c_int32)]
+                ("last_loop_ms", C.c_double), ("last_loop_sweeps", C.c_int32), ("pad_", C.c_int32),
+                ("state_gen", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,6 +88,7 @@ def lib():
             "jac_solve_async": [_vp, C.c_double, C.c_int32, C.c_int, C.c_int32, _i32p, _f64p],
             "jac_get_send_lists": [_vp, _i32p, _i32p, _i32p, _i64p],
             "jac_autotune_batched": [C.POINTER(_vp), C.c_int32, C.c_int32],
+            "jac_sweep_checkpointed": [_vp, C.c_int32, C.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -250,6 +253,10 @@ def jac_solve_batched(handles, tol, maxit):
                                  rr.ctypes.data_as(_f64p))
     _check(st)
     return st, sw, rr
+
+
+def jac_sweep_checkpointed(h, K, ckpt_every):
+    return _check(lib().jac_sweep_checkpointed(h, int(K), int(ckpt_every)))
 
 
 def jac_adjoint(h, K, ckpt_every, gx_dev, gb_dev=None, gvals_dev=None):

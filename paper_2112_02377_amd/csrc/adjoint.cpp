@@ -89,9 +89,79 @@ static void build_transpose(Handle& h)
     h.have_t = true;
 }
 
+// Checkpoint stride actually used (at most K) and the device-memory check of
+// the adjoint's buffers.
+static int32_t ckpt_stride(int32_t K, int32_t ckpt) { return std::max(1, std::min(ckpt, std::max(K, 1))); }
+
+static void check_adjoint_memory(const Handle& h, int32_t K, int32_t c)
+{
+    const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
+    const size_t vec = (size_t)h.a.n * sizeof(double);
+    const size_t need = (size_t)nseg * vec + (size_t)(2 * c + 1) * vec + 4 * vec + (size_t)h.plan.slots * 8;
+    if (need > (size_t)h.opt.ckpt_mb << 20)
+        fail(JAC_E_INVALID, "adjoint buffers exceed JAC_OPT_CKPT_MEM_MB; raise it or the checkpoint stride");
+}
+
+// K sweeps from x_0 = 0, one launch per sweep on the handle's three iterate
+// buffers (x_k in buffer k mod 3), x_{jc} copied out as checkpoint j.  Ends
+// with x_K in the handle's first buffer and the checkpoints marked valid for
+// the handle's current state.
+static void forward_ckpt(Handle& h, int32_t K, int32_t c)
+{
+    const int32_t n = h.a.n;
+    const hipStream_t st = h.stream;
+    const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
+    const size_t vec = (size_t)n * sizeof(double);
+    DeviceArrays& d = h.d;
+    d.adj_ck.ensure(std::max<size_t>((size_t)nseg * vec, 16));
+    const SysDev sA = h.sysdev(false);
+    d.sys.ensure(sizeof(SysDev));
+    JAC_HIP(hipMemcpyAsync(d.sys.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
+    d.state.ensure(sizeof(SysState));
+    JAC_HIP(hipStreamSynchronize(st));   // sA is a temporary
+    double* xb[3] = {static_cast<double*>(d.x0.p), static_cast<double*>(d.x1.p), static_cast<double*>(d.x2.p)};
+    auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
+    void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0);
+    const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
+    const size_t lds = loop_lds_bytes(fpb, runs, 0);
+    const int grid = std::max(h.plan.ntiles, 1) + 1;
+    launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, xb[0], st);
+    launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
+    LoopParams p{};
+    p.sys = static_cast<const SysDev*>(d.sys.p);
+    p.st = static_cast<SysState*>(d.state.p);
+    p.nsys = 1;
+    p.k0 = 0;
+    p.kend = K;
+    p.solve = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        if (k % c == 0) JAC_HIP(hipMemcpyAsync(CK(k / c), xb[k % 3], vec, hipMemcpyDeviceToDevice, st));
+        launch_sweep1(fn, grid, h.opt.block, lds, st, p, k, fpb, runs);
+    }
+    h.settle((uint32_t)(K % 3));
+    h.ckpt_K = K;
+    h.ckpt_c = c;
+    h.ckpt_gen = h.state_gen;
+}
+
 }  // namespace jac
 
 using namespace jac;
+
+extern "C" jac_status jac_sweep_checkpointed(jac_handle hp, int32_t K, int32_t ckpt_every)
+{
+    return guarded([&]() -> jac_status {
+        if (!hp) fail(JAC_E_INVALID, "NULL handle");
+        Handle& h = *hp;
+        if (K < 0 || ckpt_every < 1) fail(JAC_E_INVALID, "need K >= 0 and ckpt_every >= 1");
+        if (h.nrhs != 1) fail(JAC_E_INVALID, "checkpointed sweeps need a handle with one right-hand side");
+        const int32_t c = ckpt_stride(K, ckpt_every);
+        check_adjoint_memory(h, K, c);
+        ++h.state_gen;
+        forward_ckpt(h, K, c);
+        return JAC_OK;
+    });
+}
 
 extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const double* gx_dev, double* gb_dev,
                                   double* gvals_dev)
@@ -104,12 +174,10 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         const int32_t n = h.a.n;
         const int64_t nnz = h.a.nnz();
         const hipStream_t st = h.stream;
-        const int32_t c = std::max(1, std::min(ckpt, std::max(K, 1)));
+        const int32_t c = ckpt_stride(K, ckpt);
         const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
         const size_t vec = (size_t)n * sizeof(double);
-        const size_t need = (size_t)nseg * vec + (size_t)(2 * c + 1) * vec + 4 * vec + (size_t)h.plan.slots * 8;
-        if (need > (size_t)h.opt.ckpt_mb << 20)
-            fail(JAC_E_INVALID, "adjoint buffers exceed JAC_OPT_CKPT_MEM_MB; raise it or the checkpoint stride");
+        check_adjoint_memory(h, K, c);
         if (!h.have_t) build_transpose(h);
         DeviceArrays& d = h.d;
         // A^T values from A's slots (coefficients may have changed since)
@@ -149,13 +217,10 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         d.adj_segs.ensure(sizeof(SysDev) * (size_t)c);
         JAC_HIP(hipMemcpyAsync(d.adj_sys.p, desc, sizeof(desc), hipMemcpyHostToDevice, st));
         JAC_HIP(hipMemcpyAsync(d.adj_segs.p, segs.data(), sizeof(SysDev) * (size_t)c, hipMemcpyHostToDevice, st));
-        d.sys.ensure(sizeof(SysDev));
-        JAC_HIP(hipMemcpyAsync(d.sys.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
         d.state.ensure(sizeof(SysState));
         JAC_HIP(hipStreamSynchronize(st));   // the host descriptors are temporaries
         const SysDev* d_sT = static_cast<const SysDev*>(d.adj_sys.p);
         const SysDev* d_sG = d_sT + 1;
-        d.adj_ck.ensure(std::max<size_t>((size_t)nseg * vec, 16));
         d.adj_M.ensure((size_t)c * vec);
         d.adj_lam0.ensure(vec);
         d.adj_lam1.ensure(vec);
@@ -166,29 +231,18 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         JAC_HIP(hipMemsetAsync(d.adj_gb.p, 0, vec, st));
         auto Mm = [&](int m) { return static_cast<double*>(d.adj_M.p) + (size_t)m * n; };
         auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
-        double* xb[3] = {static_cast<double*>(d.x0.p), static_cast<double*>(d.x1.p), static_cast<double*>(d.x2.p)};
-
-        // forward from x_0 = 0, one launch per sweep on the handle's three
-        // iterate buffers (x_k in buffer k mod 3); x_{jc} kept as checkpoint j
+        // the forward with checkpoints, unless jac_sweep_checkpointed left
+        // them for this K and stride and nothing changed the handle since
+        if (!(h.ckpt_gen == h.state_gen && h.ckpt_K == K && h.ckpt_c == c)) {
+            ++h.state_gen;
+            forward_ckpt(h, K, c);
+        }
+        double* xK = static_cast<double*>(d.x0.p);
+        // recompute sweeps: the kernel of the forward
         void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0);
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);
         const int grid = std::max(h.plan.ntiles, 1) + 1;
-        launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, xb[0], st);
-        launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
-        {
-            LoopParams p{};
-            p.sys = static_cast<const SysDev*>(d.sys.p);
-            p.st = static_cast<SysState*>(d.state.p);
-            p.nsys = 1;
-            p.k0 = 0;
-            p.kend = K;
-            p.solve = 0;
-            for (int32_t k = 0; k < K; ++k) {
-                if (k % c == 0) JAC_HIP(hipMemcpyAsync(CK(k / c), xb[k % 3], vec, hipMemcpyDeviceToDevice, st));
-                launch_sweep1(fn, grid, h.opt.block, lds, st, p, k, fpb, runs);
-            }
-        }
         if (K > 0) {
             // lambda_K (internal order), mu_K = D^{-1} lambda_K, gb = mu_K
             double* lin = static_cast<double*>(d.adj_lam0.p);
@@ -205,8 +259,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                 // x_{k0} .. x_{k0+L}: both ends are known (checkpoints, or x_K
                 // from the forward), the sweeps in between are recomputed
                 JAC_HIP(hipMemcpyAsync(Xm(0), CK(j), vec, hipMemcpyDeviceToDevice, st));
-                JAC_HIP(hipMemcpyAsync(Xm(L), j + 1 < nseg ? CK(j + 1) : xb[K % 3], vec, hipMemcpyDeviceToDevice,
-                                       st));
+                JAC_HIP(hipMemcpyAsync(Xm(L), j + 1 < nseg ? CK(j + 1) : xK, vec, hipMemcpyDeviceToDevice, st));
                 for (int32_t m = 0; m + 1 < L; ++m) {
                     LoopParams p{};
                     p.sys = static_cast<const SysDev*>(d.adj_segs.p) + m;
@@ -229,8 +282,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                 if (j > 0) JAC_HIP(hipMemcpyAsync(Mm(c - 1), d.adj_carry.p, vec, hipMemcpyDeviceToDevice, st));
             }
         }
-        // the handle keeps x_K in its first iterate buffer
-        h.settle((uint32_t)(K % 3));
+        // the handle keeps x_K (and the checkpoints stay valid)
         if (gb_dev)
             launch_scatter_out(static_cast<const double*>(d.adj_gb.p), static_cast<const int32_t*>(d.perm.p), n, 1,
                                gb_dev, st);

@@ -71,6 +71,7 @@ Handle::~Handle()
 // Rebuild the split and the sliced layout; keeps values, b and x.
 void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
 {
+    ++state_gen;
     // current x out to caller order (device) before the order changes
     DevMem xsave;
     if (planned) {
@@ -488,6 +489,7 @@ jac_status jac_set_values(jac_handle h, const double* vals_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h || !vals_dev) fail(JAC_E_INVALID, "NULL argument");
+        ++h->state_gen;
         DevMem old;
         old.alloc((size_t)h->a.nnz() * sizeof(double));
         JAC_HIP(hipMemcpyAsync(old.p, h->d.vals_caller.p, (size_t)h->a.nnz() * sizeof(double),
@@ -510,6 +512,7 @@ jac_status jac_set_rhs(jac_handle h, const double* b_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h || !b_dev) fail(JAC_E_INVALID, "NULL argument");
+        ++h->state_gen;
         JAC_HIP(hipMemcpyAsync(h->d.b_caller.p, b_dev, (size_t)h->a.n * h->nrhs * sizeof(double),
                                hipMemcpyDeviceToDevice, h->stream));
         launch_gather_in(static_cast<const double*>(h->d.b_caller.p), static_cast<const int32_t*>(h->d.perm.p),
@@ -596,6 +599,7 @@ jac_status jac_set_x(jac_handle h, const double* x_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        ++h->state_gen;
         launch_gather_in(x_dev, static_cast<const int32_t*>(h->d.perm.p), h->a.n, h->nrhs,
                          static_cast<double*>(h->d.x0.p), h->stream);
         return JAC_OK;
@@ -617,6 +621,7 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double* hist_dev)
         if (!h) fail(JAC_E_INVALID, "NULL handle");
         if (nsweeps < 0) fail(JAC_E_INVALID, "nsweeps must be >= 0");
         if (nsweeps == 0) return JAC_OK;
+        ++h->state_gen;
         std::vector<SysDev> sys = {h->sysdev(false)};
         std::vector<int32_t> tb = {0, h->plan.ntiles};
         run_loop(*h, sys, false, false, nsweeps, 0, hist_dev, h->d.sys, h->d.state, h->d.tile_base, tb,
@@ -666,6 +671,7 @@ jac_status jac_solve(jac_handle h, double tol, int32_t maxit, jac_norm norm, jac
         if (!h) fail(JAC_E_INVALID, "NULL handle");
         if (!(tol >= 0.0) || maxit < 0) fail(JAC_E_INVALID, "tol must be >= 0 and maxit >= 0");
         if (norm != JAC_NORM_L2_REL && norm != JAC_NORM_INF_ABS) fail(JAC_E_INVALID, "bad norm");
+        ++h->state_gen;
         if (prec == JAC_FP64) return solve64(*h, tol, maxit, norm, sweeps_out, relres_out);
         if (prec == JAC_FP32_REFINE) return solve_refine(*h, tol, maxit, norm, sweeps_out, relres_out);
         fail(JAC_E_INVALID, "bad precision");
@@ -692,6 +698,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
             if (h.nrhs != nrhs || h.plan.colfmt != colfmt)
                 fail(JAC_E_INVALID, "all handles of a batch need the same nrhs and column format");
             if (h.device != h0.device) fail(JAC_E_INVALID, "all handles of a batch must be on one device");
+            ++h.state_gen;
             SysDev d = h.sysdev(false);
             for (int c = 0; c < 4; ++c) {
                 const double bn = h.bnorm[c];
@@ -822,6 +829,7 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.block = h->opt.block;
         i.last_loop_ms = h->last_loop_ms;
         i.last_loop_sweeps = h->last_loop_sweeps;
+        i.state_gen = h->state_gen;
         *info = i;
         return JAC_OK;
     });

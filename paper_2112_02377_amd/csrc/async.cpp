@@ -31,6 +31,7 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
         if (norm != JAC_NORM_L2_REL && norm != JAC_NORM_INF_ABS) fail(JAC_E_INVALID, "bad norm");
         if (rounds_per_check < 1) fail(JAC_E_INVALID, "rounds_per_check must be >= 1");
         Handle& h = *hp;
+        ++h.state_gen;
         const int32_t n = h.a.n, nr = h.nrhs;
         const hipStream_t st = h.stream;
         const int norm_inf = norm == JAC_NORM_INF_ABS ? 1 : 0;

@@ -89,6 +89,12 @@ struct Handle {
     ~Handle();
     // adjoint: plan of A^T (built on first use)
     bool have_t = false;
+    // state counter: raised by every call that changes the system, its split
+    // or x; the checkpoints of jac_sweep_checkpointed stay valid while it
+    // keeps the value it had when they were taken
+    int64_t state_gen = 1;
+    int64_t ckpt_gen = 0;
+    int32_t ckpt_K = -1, ckpt_c = 0;
     Plan tplan;
     DeviceArrays td;
 

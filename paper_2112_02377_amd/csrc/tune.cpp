@@ -89,6 +89,7 @@ extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
         if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
         Handle& h = *hp;
+        ++h.state_gen;
         const std::string key = cache_key(h);
         const int32_t* sub = h.part_has_sub ? h.part_sub : nullptr;
         int32_t rows = 0, block = 0;
@@ -141,6 +142,7 @@ extern "C" jac_status jac_autotune_batched(const jac_handle* hs, int32_t nsys, i
         if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
         for (int32_t s = 0; s < nsys; ++s)
             if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
+        for (int32_t s = 0; s < nsys; ++s) ++hs[s]->state_gen;
         static const Cand kBatch[] = {{256, 256}, {512, 256}, {1024, 256}, {2048, 256}};
         Handle& h0 = *hs[0];
         int64_t sum_n = 0, sum_nnz = 0;

@@ -134,3 +134,61 @@ def test_full_size_theta_gradient_against_central_differences():
     gp = g[s.extra["probes"]]
     assert np.all(np.abs(gp - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())), (gp, fd)
     b.jac_destroy(h)
+
+
+def test_checkpointed_forward_is_reused_and_invalidated():
+    need_gpu()
+    b = B()
+    s = W.diffusion_adjoint(12)
+    K, c = 90, 7
+    h = make(s, 2, 3)
+    st, xo, _ = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    g = xo - s.extra["x_target"]
+    # forward kept on the device: the same iterate as K plain sweeps
+    b.jac_sweep_checkpointed(h, K, c)
+    assert rel_inf(get_x(h, s.n)[0], xo) <= 1e-12
+    gen = b.jac_get_info(h)["state_gen"]
+    gb1, gv1 = run_adjoint(h, K, c, g, s.n, s.nnz)          # reuses the checkpoints
+    assert b.jac_get_info(h)["state_gen"] == gen
+    b.jac_set_x(h, None)                                    # any change invalidates them
+    assert b.jac_get_info(h)["state_gen"] > gen
+    gb2, gv2 = run_adjoint(h, K, c, g, s.n, s.nnz)          # takes them again
+    assert np.array_equal(gb1, gb2) and np.array_equal(gv1, gv2)
+    sto, gbo, gvo, _ = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K, g)
+    assert np.abs(gb1 - gbo).max() <= 1e-10 * np.abs(gbo).max()
+    assert np.abs(gv1 - gvo).max() <= 1e-10 * np.abs(gvo).max()
+    # a different K or stride does not reuse them; new values are picked up
+    b.jac_sweep_checkpointed(h, K, c)
+    gb3, _ = run_adjoint(h, K - 5, c, g, s.n, s.nnz)
+    _, gbo3, _, _ = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K - 5, g)
+    assert np.abs(gb3 - gbo3).max() <= 1e-10 * np.abs(gbo3).max()
+    b.jac_sweep_checkpointed(h, K, c)
+    v2 = s.vals * 1.01
+    b.jac_set_values(h, dev(v2))
+    gb4, gv4 = run_adjoint(h, K, c, g, s.n, s.nnz)
+    _, gbo4, gvo4, _ = ref.adjoint(s.row_ptr, s.col_idx, v2, s.b[0], K, g)
+    assert np.abs(gv4 - gvo4).max() <= 1e-10 * np.abs(gvo4).max()
+    b.jac_destroy(h)
+
+
+def test_autograd_backward_after_the_handle_was_used_again():
+    # backward restores the system when the handle was used in between
+    need_gpu()
+    from paper_2112_02377_amd.autograd import JacobiK, diffusion_values
+    b = B()
+    s = W.diffusion_adjoint(8)
+    t = dev(s.extra["x_target"])
+    h = make(s, 1, 2)
+    grads = []
+    for touch in (False, True):
+        theta = dev(s.extra["theta"]).requires_grad_(True)
+        vals = diffusion_values(theta, s.grid, s.row_ptr, s.extra["slot"])
+        x = JacobiK.apply(vals, dev(s.b[0]), h, 60, 9)
+        if touch:
+            b.jac_set_values(h, dev(s.vals * 2.0))
+            b.jac_set_x(h, None)
+            b.jac_sweep(h, 5)
+        (0.5 * ((x - t) ** 2).sum()).backward()
+        grads.append(theta.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1])
+    b.jac_destroy(h)
