@@ -495,13 +495,14 @@ def main():
                        "dev_GBps": round(i["dev_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
                        "col_bytes": i["col_bytes"], "halo_entries": i["halo_entries"],
                        "staged_entries": i["staged_entries"], "ntiles": i["ntiles"], "grid": i["loop_grid"],
-                       "setup_s": round(setup_s[m], 2)}
+                       "matrix_loads": "kept" if i["keep_matrix"] else "streamed", "setup_s": round(setup_s[m], 2)}
     # dominant kernel: the loop instantiation with the most time per step
     kern = {}
     for m in sel:
         kname = "k_loop" if args.loop else "k_sweep"
         cm = 2 if m in ("JBO", "JSS") else (1 if infos[m]["col_bytes"] == 2 else 0)
-        tag = f"{kname}<double, 1, {cm}>"
+        nt = "false" if infos[m]["keep_matrix"] else "true"       # nontemporal matrix loads
+        tag = f"{kname}<double, 1, {cm}, {nt}>"
         kern.setdefault(tag, []).append(m)
     dom = max(kern, key=lambda t: sum(per_mode[m]["loop_ms"] for m in kern[t]))
     dm = kern[dom]

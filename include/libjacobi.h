@@ -87,7 +87,7 @@ typedef enum {
     JAC_OPT_TIMING = 9,      /* 1 = time each sweep loop with HIP events on the
                                 handle's stream (jac_info.last_loop_ms); the call
                                 then waits for the loop to finish                  */
-    JAC_OPT_PARTITIONER = 10 /* how jac_partition forms parts / subdomains:
+    JAC_OPT_PARTITIONER = 10,/* how jac_partition forms parts / subdomains:
                                 0 = equal row counts and grid blocks (default);
                                 1 = equal stored-entry counts (contiguous bands;
                                     JAC_SUBSTRUCT without a grid: contiguous
@@ -95,6 +95,12 @@ typedef enum {
                                 2 = weighted graph partition (jac_graph_partition:
                                     parts of the band-row modes, subdomains of
                                     JAC_SUBSTRUCT), rows renumbered part by part */
+    JAC_OPT_CACHE = 11       /* matrix loads of a sweep: 0 = auto (default: kept in
+                                the caches when one sweep streams at most 240 MiB,
+                                which the 256 MB Infinity Cache then holds across
+                                sweeps; else streamed with the nontemporal hint);
+                                1 = always kept; 2 = always streamed.  A batched
+                                solve decides on the bytes of the whole batch  */
 } jac_option;
 
 typedef struct {
@@ -112,7 +118,8 @@ typedef struct {
     int32_t block;               /* threads per workgroup                           */
     double last_loop_ms;         /* duration of the last sweep loop (JAC_OPT_TIMING) */
     int32_t last_loop_sweeps;    /* sweeps that loop ran (incl. a final test sweep)  */
-    int32_t pad_;
+    int32_t keep_matrix;         /* 1 = a sweep of this handle alone loads the matrix
+                                    with temporal hints (JAC_OPT_CACHE)              */
     int64_t state_gen;           /* raised by every call that changes the system, its
                                     split or x (checkpoints stay valid while it holds) */
 } jac_info;

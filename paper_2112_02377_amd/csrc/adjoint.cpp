@@ -121,7 +121,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
     JAC_HIP(hipStreamSynchronize(st));   // sA is a temporary
     double* xb[3] = {static_cast<double*>(d.x0.p), static_cast<double*>(d.x1.p), static_cast<double*>(d.x2.p)};
     auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
-    void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0);
+    void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
     const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
     const size_t lds = loop_lds_bytes(fpb, runs, 0);
     const int grid = std::max(h.plan.ntiles, 1) + 1;
@@ -197,7 +197,10 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         sT.ntiles = h.tplan.ntiles;
         sT.nrhs = 1;
         sT.colfmt = h.tplan.colfmt;
-        const SysDev sA = h.sysdev(false);
+        // reverse steps stream A^T and the recomputed sweeps A: both count
+        sT.keep = keep_matrix(h.opt.cache, 2 * h.stream_bytes(false));
+        SysDev sA = h.sysdev(false);
+        sA.keep = sT.keep;
         desc[1] = sA;
         int gfmt = h.plan.colfmt;
         if (gfmt == COL_LOCAL16) {
@@ -239,7 +242,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         }
         double* xK = static_cast<double*>(d.x0.p);
         // recompute sweeps: the kernel of the forward
-        void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0);
+        void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);
         const int grid = std::max(h.plan.ntiles, 1) + 1;
@@ -274,7 +277,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                     const int32_t k = k0 + m;
                     double* mu_out = nullptr;
                     if (k >= 1) mu_out = m >= 1 ? Mm(m - 1) : static_cast<double*>(d.adj_carry.p);
-                    launch_adj_step(h.tplan.colfmt, h.tplan.ntiles, st, d_sT, lin, Mm(m), lout, mu_out,
+                    launch_adj_step(h.tplan.colfmt, sT.keep != 0, h.tplan.ntiles, st, d_sT, lin, Mm(m), lout, mu_out,
                                     static_cast<double*>(d.adj_gb.p), static_cast<const double*>(d.invd.p));
                     std::swap(lin, lout);
                 }

@@ -193,6 +193,28 @@ void Handle::get_x_dev(double* out)
                        stream);
 }
 
+int64_t sweep_stream_bytes(int64_t slots, int colfmt, int32_t n, int nrhs, bool fp32)
+{
+    const int64_t t = fp32 ? 4 : 8;
+    return slots * (t + (colfmt == COL_GLOBAL32 ? 4 : 2)) + 3 * t * (int64_t)n * nrhs;
+}
+
+// Auto: a launch whose sweep streams at most kKeepBytes keeps its matrix in
+// the 256 MB Infinity Cache across sweeps; a larger one would only thrash it
+// and evict the x entries that are gathered again.
+int32_t keep_matrix(int32_t policy, int64_t bytes)
+{
+    constexpr int64_t kKeepBytes = 240ll << 20;
+    if (policy == 1) return 1;
+    if (policy == 2) return 0;
+    return bytes <= kKeepBytes ? 1 : 0;
+}
+
+int64_t Handle::stream_bytes(bool fp32) const
+{
+    return sweep_stream_bytes(plan.slots, plan.colfmt, a.n, nrhs, fp32);
+}
+
 SysDev Handle::sysdev(bool fp32) const
 {
     SysDev s{};
@@ -225,6 +247,7 @@ SysDev Handle::sysdev(bool fp32) const
     s.nrhs = nrhs;
     s.staged = plan.prm.staged ? 1 : 0;
     s.colfmt = plan.colfmt;
+    s.keep = keep_matrix(opt.cache, stream_bytes(fp32));
     for (int c = 0; c < 4; ++c) { s.thr[c] = 0.0; s.big[c] = 1e300; }
     return s;
 }
@@ -289,13 +312,14 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     h.last_loop_sweeps = kend;
     const int64_t work = tile_base.back();
     const int block = h.opt.block;
+    const bool keep = !sys.empty() && sys[0].keep != 0;    // one choice for every system of the launch
     if (h.opt.timing) {
         for (auto& e : h.ev)
             if (!e) JAC_HIP(hipEventCreate(&e));
         JAC_HIP(hipEventRecord(h.ev[0], st));
     }
     if (h.opt.loop == 1) {
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, 1);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 1, keep);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, nsys);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, work);
         h.last_grid = grid;
@@ -306,7 +330,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         // waits for it) and drops stopped systems from the list; a stopped
         // system still on the list costs its tiles an early return.
         if (!solve) fail(JAC_E_INVALID, "several systems are swept in solve mode only");
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, 2);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 2, keep);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
         const size_t wl_ints = 2 * (size_t)nsys + 1;
         const size_t host_bytes = (size_t)nsys * sizeof(SysState) + 2 * wl_ints * sizeof(int32_t);
@@ -370,7 +394,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         }
         if (!all_done) launch_decide_multi(nrhs, st, p, kend);
     } else {
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, 0);
+        void* fn = sweep_kernel(fp32, nrhs, colfmt, 0, keep);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
         const int grid = (int)std::max<int64_t>(1, work) + 1;      // + the deciding workgroup
         h.last_grid = grid;
@@ -711,6 +735,10 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
             fpb = std::max(fpb, h.lds_fp_bytes(false));
             runs = std::max(runs, h.lds_runs());
         }
+        // every sweep of the batch streams all its systems: one cache choice
+        int64_t bytes = 0;
+        for (int32_t s = 0; s < nsys; ++s) bytes += hs[s]->stream_bytes(false);
+        for (SysDev& d : sys) d.keep = keep_matrix(h0.opt.cache, bytes);
         for (int32_t s = 1; s < nsys; ++s) hs[s]->sync();
         upload(h0.d.batch_tile_base, tb, h0.stream);
         run_loop(h0, sys, false, true, maxit, 0, nullptr, h0.d.batch_sys, h0.d.batch_state, h0.d.batch_tile_base, tb,
@@ -774,6 +802,9 @@ jac_status jac_set_option(jac_handle h, jac_option opt, int64_t v)
         case JAC_OPT_PARTITIONER:
             if (v < 0 || v > 2) fail(JAC_E_INVALID, "partitioner: 0, 1 or 2");
             o.partitioner = (int32_t)v; break;
+        case JAC_OPT_CACHE:
+            if (v < 0 || v > 2) fail(JAC_E_INVALID, "cache policy: 0, 1 or 2");
+            o.cache = (int32_t)v; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -796,6 +827,7 @@ jac_status jac_get_option(jac_handle h, jac_option opt, int64_t* v)
         case JAC_OPT_CKPT_MEM_MB: *v = o.ckpt_mb; break;
         case JAC_OPT_TIMING: *v = o.timing; break;
         case JAC_OPT_PARTITIONER: *v = o.partitioner; break;
+        case JAC_OPT_CACHE: *v = o.cache; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -829,6 +861,7 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.block = h->opt.block;
         i.last_loop_ms = h->last_loop_ms;
         i.last_loop_sweeps = h->last_loop_sweeps;
+        i.keep_matrix = keep_matrix(h->opt.cache, h->stream_bytes(false));
         i.state_gen = h->state_gen;
         *info = i;
         return JAC_OK;

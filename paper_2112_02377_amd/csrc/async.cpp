@@ -50,7 +50,7 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
         JAC_HIP(hipMemcpyAsync(d.async_sys.p, &s, sizeof(SysDev), hipMemcpyHostToDevice, st));
         JAC_HIP(hipStreamSynchronize(st));                      // s is a temporary
         const SysDev* dsys = static_cast<const SysDev*>(d.async_sys.p);
-        void* fn = async_kernel(nr, h.plan.colfmt);
+        void* fn = async_kernel(nr, h.plan.colfmt, s.keep != 0);
         const int block = h.opt.block;
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);

@@ -39,7 +39,16 @@ struct Options {
     int64_t ckpt_mb = 4096;
     int32_t timing = 0;
     int32_t partitioner = 0;
+    int32_t cache = 0;         // matrix loads: 0 auto, 1 keep in cache, 2 stream (nontemporal)
 };
+
+// Bytes one sweep streams from memory when the matrix is loaded from the
+// caches no more than once: values and column entries of every stored slot,
+// and b, x_k and x_{k+1}.
+int64_t sweep_stream_bytes(int64_t slots, int colfmt, int32_t n, int nrhs, bool fp32);
+// The temporal/nontemporal choice for matrix loads of a launch that streams
+// `bytes` per sweep under cache policy `policy`.
+int32_t keep_matrix(int32_t policy, int64_t bytes);
 
 struct DeviceArrays {
     DevMem tile_row0, tile_slice0, slice_row0, slice_width, slice_off;
@@ -106,6 +115,7 @@ struct Handle {
     void get_x_dev(double* out);
     void settle(uint32_t which);
     SysDev sysdev(bool fp32) const;
+    int64_t stream_bytes(bool fp32) const;
     int lds_fp_bytes(bool fp32) const;
     int lds_runs() const;
 };

@@ -30,6 +30,9 @@ struct SysDev {
     void* x[3];               // iterate buffers, T, node-major [n][nrhs]; x_k lives in x[k % 3]
     double* tile_part;        // [2][ntiles][nrhs] per-tile norm partials, by sweep parity
     int32_t n, ntiles, nrhs, staged, colfmt;
+    int32_t keep;             // matrix loads: 1 temporal (may stay in the caches),
+                              // 0 nontemporal; the host launches the kernel
+                              // instantiation that matches
     double thr[4];            // stop thresholds per right-hand side
     double big[4];            // divergence thresholds per right-hand side
 };

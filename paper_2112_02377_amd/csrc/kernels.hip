@@ -157,7 +157,34 @@ __device__ __forceinline__ void stx_dev(V* p, V v)
     __hip_atomic_store((gptr<V>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int NRHS, int CM, bool RESID = false, bool COH = false>
+// One batch of a slice's stored slots k0 .. k0+KB-1 (those below w): values
+// and raw column entries.  NT loads them with the nontemporal hint, which
+// keeps a matrix too large for the caches from evicting the x entries that
+// are gathered again; a matrix that fits (the 256 MB Infinity Cache) is
+// loaded normally so that the next sweep finds it there.
+template <bool NT, typename V>
+__device__ __forceinline__ V ldm(gptr<const V> p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T, int CM>
+__device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t> col32, gptr<const uint16_t> col16,
+                                           int64_t off, int32_t k0, int32_t w, T (&a)[KB], int32_t (&raw)[KB])
+{
+#pragma unroll
+    for (int u = 0; u < KB; ++u)
+        if (k0 + u < w) {
+            const int64_t slot = off + (int64_t)(k0 + u) * 64;
+            a[u] = ldm<NT>(&val[slot]);
+            if constexpr (CM == COL_GLOBAL32) raw[u] = ldm<NT>(&col32[slot]);
+            else if constexpr (CM == COL_REL16) raw[u] = (int16_t)ldm<NT>(&col16[slot]);
+            else raw[u] = ldm<NT>(&col16[slot]);
+        }
+}
+
+// NT: matrix loads with the nontemporal hint (the host chooses per launch).
+template <typename T, int NRHS, int CM, bool NT, bool RESID = false, bool COH = false>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
                                            bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
                                            int32_t* __restrict__ lds_ro, double (&acc)[NRHS],
@@ -252,15 +279,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             // so that none waits for another
             T a[KB];
             int32_t raw[KB];
-#pragma unroll
-            for (int u = 0; u < KB; ++u)
-                if (k0 + u < w) {
-                    const int64_t slot = off + (int64_t)(k0 + u) * 64;
-                    a[u] = __builtin_nontemporal_load(&val[slot]);
-                    if constexpr (CM == COL_GLOBAL32) raw[u] = __builtin_nontemporal_load(&col32[slot]);
-                    else if constexpr (CM == COL_REL16) raw[u] = (int16_t)__builtin_nontemporal_load(&col16[slot]);
-                    else raw[u] = __builtin_nontemporal_load(&col16[slot]);
-                }
+            load_batch<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
             int32_t col[KB];
             T xv[KB][NRHS];
 #pragma unroll
@@ -306,6 +325,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     // LDS is reused by the next tile: every caller follows with block_reduce,
     // whose barrier all waves pass only after their last slice
 }
+
 
 // Reduce the tile partials of sweep k of system s in tile order and take the
 // stop decision on r_k.  DEV selects coherent accesses (persistent launch,
@@ -362,7 +382,7 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
 // One launch per sweep (single system).  Workgroups 0..ntiles-1 sweep one tile
 // each; the last workgroup takes the stop decision on the previous sweep.
 // ---------------------------------------------------------------------------
-template <typename T, int NRHS, int CM>
+template <typename T, int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
@@ -391,7 +411,7 @@ __global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t 
         double acc[NRHS];
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-        sweep_tile<T, NRHS, CM>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        sweep_tile<T, NRHS, CM, NT>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -416,7 +436,7 @@ __global__ void __launch_bounds__(512) k_decide(LoopParams P, int32_t k)
 // workgroup of a single-system launch does.  A system that stopped is
 // skipped by its tiles and left alone by its decider (the host drops it from
 // the list a little later).
-template <typename T, int NRHS, int CM>
+template <typename T, int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, const int32_t* __restrict__ wl,
                                                     int32_t nact, int32_t lds_fp_bytes, int32_t lds_runs)
 {
@@ -454,8 +474,8 @@ __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, co
         double acc[NRHS];
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-        sweep_tile<T, NRHS, CM>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]), reinterpret_cast<T*>(S.x[(k + 1) % 3]),
-                                frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        sweep_tile<T, NRHS, CM, NT>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
+                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs, lds_ro, acc);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
             double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
@@ -472,7 +492,7 @@ __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, co
 // age; loads and stores of x are device-coherent, so every update becomes
 // visible to the other workgroups.  The stop test is left to the host, on
 // the quiescent x between launches.
-template <int NRHS, int CM>
+template <int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds, int32_t lds_fp_bytes,
                                               int32_t lds_runs)
 {
@@ -489,7 +509,7 @@ __global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds
             double acc[NRHS];
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-            sweep_tile<double, NRHS, CM, false, true>(S, tile, x, x, 0u, false, lds_x, lds_rs, lds_ro, acc);
+            sweep_tile<double, NRHS, CM, NT, false, true>(S, tile, x, x, 0u, false, lds_x, lds_rs, lds_ro, acc);
             if constexpr (CM == COL_LOCAL16) __syncthreads();    // the next tile restages the LDS
         }
 }
@@ -507,6 +527,8 @@ __global__ void __launch_bounds__(512) k_decide_multi(LoopParams P, int32_t k)
 // FP64 residual for mixed-precision refinement: r = b - A x with the FP64
 // coefficients, written as FP32 (the right-hand side of the inner FP32
 // sweeps; columns in `frozen` get 0), plus the FP64 norm partial per tile.
+// The FP64 matrix is read once per outer step, so it is streamed
+// (nontemporal) and leaves the caches to the FP32 copy of the inner sweeps.
 // ---------------------------------------------------------------------------
 template <int NRHS, int CM>
 __global__ void __launch_bounds__(512) k_resid(const SysDev* sys, float* r32, uint32_t frozen, int32_t norm_inf,
@@ -525,8 +547,8 @@ __global__ void __launch_bounds__(512) k_resid(const SysDev* sys, float* r32, ui
         double acc[NRHS];
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-        sweep_tile<double, NRHS, CM, true>(S, tile, reinterpret_cast<const double*>(S.x[0]), nullptr, frozen,
-                                           is_max, lds_x, lds_rs, lds_ro, acc, r32);
+        sweep_tile<double, NRHS, CM, true, true>(S, tile, reinterpret_cast<const double*>(S.x[0]), nullptr, frozen,
+                                                 is_max, lds_x, lds_rs, lds_ro, acc, r32);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -647,7 +669,7 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
 // sweep k leaves it from sweep k+2, so a racing read cannot change the list);
 // (C) tiles; (D) barrier.  The third iterate buffer keeps x_k intact while
 // sweep k+1 runs before the decision on r_k is known.
-template <typename T, int NRHS, int CM>
+template <typename T, int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
@@ -684,7 +706,7 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
             double acc[NRHS];
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-            sweep_tile<T, NRHS, CM>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
+            sweep_tile<T, NRHS, CM, NT>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
                                     reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs, lds_ro,
                                     acc);
             block_reduce<NRHS>(acc, is_max, red);
@@ -813,32 +835,32 @@ namespace {
 
 // loop: 0 = one launch per sweep, 1 = persistent loop, 2 = one launch per
 // sweep over a list of systems
-template <typename T, int NRHS, int CM>
+template <typename T, int NRHS, int CM, bool NT>
 void* kfn(int loop)
 {
-    if (loop == 1) return reinterpret_cast<void*>(&k_loop<T, NRHS, CM>);
-    if (loop == 2) return reinterpret_cast<void*>(&k_sweep_multi<T, NRHS, CM>);
-    return reinterpret_cast<void*>(&k_sweep<T, NRHS, CM>);
+    if (loop == 1) return reinterpret_cast<void*>(&k_loop<T, NRHS, CM, NT>);
+    if (loop == 2) return reinterpret_cast<void*>(&k_sweep_multi<T, NRHS, CM, NT>);
+    return reinterpret_cast<void*>(&k_sweep<T, NRHS, CM, NT>);
 }
 
-template <typename T, int NRHS>
+template <typename T, int NRHS, bool NT>
 void* pick_cm(int colfmt, int loop)
 {
     switch (colfmt) {
-    case COL_GLOBAL32: return kfn<T, NRHS, COL_GLOBAL32>(loop);
-    case COL_REL16: return kfn<T, NRHS, COL_REL16>(loop);
-    case COL_LOCAL16: return kfn<T, NRHS, COL_LOCAL16>(loop);
+    case COL_GLOBAL32: return kfn<T, NRHS, COL_GLOBAL32, NT>(loop);
+    case COL_REL16: return kfn<T, NRHS, COL_REL16, NT>(loop);
+    case COL_LOCAL16: return kfn<T, NRHS, COL_LOCAL16, NT>(loop);
     default: return nullptr;
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 void* pick(int nrhs, int colfmt, int loop)
 {
     switch (nrhs) {
-    case 1: return pick_cm<T, 1>(colfmt, loop);
-    case 2: return pick_cm<T, 2>(colfmt, loop);
-    case 4: return pick_cm<T, 4>(colfmt, loop);
+    case 1: return pick_cm<T, 1, NT>(colfmt, loop);
+    case 2: return pick_cm<T, 2, NT>(colfmt, loop);
+    case 4: return pick_cm<T, 4, NT>(colfmt, loop);
     default: return nullptr;
     }
 }
@@ -853,9 +875,10 @@ int grid1d(int64_t m, int block = 256)
 
 }  // namespace
 
-void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop)
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop, bool keep)
 {
-    void* f = fp32 ? pick<float>(nrhs, colfmt, loop) : pick<double>(nrhs, colfmt, loop);
+    void* f = fp32 ? (keep ? pick<float, false>(nrhs, colfmt, loop) : pick<float, true>(nrhs, colfmt, loop))
+                   : (keep ? pick<double, false>(nrhs, colfmt, loop) : pick<double, true>(nrhs, colfmt, loop));
     if (!f) fail(JAC_E_INVALID, "no sweep kernel for this right-hand-side count / column format");
     return f;
 }
@@ -900,22 +923,22 @@ void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k)
     JAC_HIP(hipGetLastError());
 }
 
-template <int NRHS>
+template <int NRHS, bool NT>
 void* async_cm(int colfmt)
 {
     switch (colfmt) {
-    case COL_GLOBAL32: return reinterpret_cast<void*>(&k_async<NRHS, COL_GLOBAL32>);
-    case COL_REL16: return reinterpret_cast<void*>(&k_async<NRHS, COL_REL16>);
-    default: return reinterpret_cast<void*>(&k_async<NRHS, COL_LOCAL16>);
+    case COL_GLOBAL32: return reinterpret_cast<void*>(&k_async<NRHS, COL_GLOBAL32, NT>);
+    case COL_REL16: return reinterpret_cast<void*>(&k_async<NRHS, COL_REL16, NT>);
+    default: return reinterpret_cast<void*>(&k_async<NRHS, COL_LOCAL16, NT>);
     }
 }
 
-void* async_kernel(int nrhs, int colfmt)
+void* async_kernel(int nrhs, int colfmt, bool keep)
 {
     switch (nrhs) {
-    case 1: return async_cm<1>(colfmt);
-    case 2: return async_cm<2>(colfmt);
-    case 4: return async_cm<4>(colfmt);
+    case 1: return keep ? async_cm<1, false>(colfmt) : async_cm<1, true>(colfmt);
+    case 2: return keep ? async_cm<2, false>(colfmt) : async_cm<2, true>(colfmt);
+    case 4: return keep ? async_cm<4, false>(colfmt) : async_cm<4, true>(colfmt);
     default: fail(JAC_E_INVALID, "no asynchronous kernel for this right-hand-side count");
     }
 }
@@ -1059,7 +1082,7 @@ __global__ void k_adj_init(const double* __restrict__ invd, const double* __rest
 
 // One reverse step on the sliced layout of A^T: lam_out = lam_in - A^T mu;
 // when mu_out is given, also mu_out = D^{-1} lam_out and gb += mu_out.
-template <int CM>
+template <int CM, bool NT>
 __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const double* __restrict__ lam_in,
                                                  const double* __restrict__ mu_, double* __restrict__ lam_out,
                                                  double* __restrict__ mu_out, double* __restrict__ gb,
@@ -1091,14 +1114,7 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
             for (int32_t k0 = 0; k0 < w; k0 += KB) {
                 double a[KB];
                 int32_t raw[KB];
-#pragma unroll
-                for (int u = 0; u < KB; ++u)
-                    if (k0 + u < w) {
-                        const int64_t slot = off + (int64_t)(k0 + u) * 64;
-                        a[u] = __builtin_nontemporal_load(&val[slot]);
-                        if constexpr (CM == COL_GLOBAL32) raw[u] = __builtin_nontemporal_load(&col32[slot]);
-                        else raw[u] = (int16_t)__builtin_nontemporal_load(&col16[slot]);
-                    }
+                load_batch<NT, double, CM>(val, col32, col16, off, k0, w, a, raw);
                 double mv[KB];
 #pragma unroll
                 for (int u = 0; u < KB; ++u)
@@ -1209,14 +1225,19 @@ void launch_adj_init(const double* invd, const double* lam, int32_t n, double* m
     JAC_HIP(hipGetLastError());
 }
 
-void launch_adj_step(int colfmt, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
+void launch_adj_step(int colfmt, bool keep, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
                      const double* mu, double* lam_out, double* mu_out, double* gb, const double* invd)
 {
+    const int g = std::max(ntiles, 1);
     // global or row-relative columns only: tile-local offsets need the staged footprint
-    if (colfmt == COL_REL16)
-        k_adj_step<COL_REL16><<<std::max(ntiles, 1), 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    if (colfmt == COL_REL16 && keep)
+        k_adj_step<COL_REL16, false><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else if (colfmt == COL_REL16)
+        k_adj_step<COL_REL16, true><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else if (colfmt == COL_GLOBAL32 && keep)
+        k_adj_step<COL_GLOBAL32, false><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
     else if (colfmt == COL_GLOBAL32)
-        k_adj_step<COL_GLOBAL32><<<std::max(ntiles, 1), 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+        k_adj_step<COL_GLOBAL32, true><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
     else
         fail(JAC_E_INVALID, "adjoint step needs global or row-relative columns");
     JAC_HIP(hipGetLastError());

@@ -13,7 +13,7 @@ namespace jac {
 // Kernel of the fused sweep for an element type, right-hand-side count
 // (1, 2 or 4), column format (ColFormat) and loop kind (0 = one launch per
 // sweep, 1 = persistent loop, 2 = one launch per sweep over a system list).
-void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop);
+void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop, bool keep);
 size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys);
 void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int lds_fp_bytes,
                  int lds_runs, bool cooperative);
@@ -25,7 +25,7 @@ void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t s
                         const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs);
 void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k);
 // asynchronous relaxation: `rounds` in-place passes over the tiles, x = sys->x[0]
-void* async_kernel(int nrhs, int colfmt);
+void* async_kernel(int nrhs, int colfmt, bool keep);
 void launch_async(void* fn, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys, int rounds,
                   int lds_fp_bytes, int lds_runs);
 // mixed-precision refinement
@@ -37,7 +37,7 @@ void launch_add_correction(double* x, const float* d0, const float* d1, const fl
 
 // adjoint
 void launch_adj_init(const double* invd, const double* lam, int32_t n, double* mu, double* gb, hipStream_t st);
-void launch_adj_step(int colfmt, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
+void launch_adj_step(int colfmt, bool keep, int ntiles, hipStream_t st, const SysDev* sysT, const double* lam_in,
                      const double* mu, double* lam_out, double* mu_out, double* gb, const double* invd);
 void launch_adj_grad(int colfmt, int ntiles, hipStream_t st, const SysDev* sysA, const double* X, const double* M,
                      int32_t L, double* G);
