@@ -155,6 +155,7 @@ def secondary(B, W, torch, stream, with_oracle=True):
         ref_err["oracle_sweeps"] = int(ko)
     out["fp32_refine"] = {
         "workload": f"fe27 96^3 (n={s.n}, nnz={s.nnz}), 1.05-dominant, tol 1e-10, 64 bands",
+        "fp64_matrix_loads": "kept" if info["keep_matrix"] else "streamed",
         "fp64_ms": res["fp64"]["ms"], "fp64_sweeps": res["fp64"]["sweeps"], "fp64_relres": res["fp64"]["relres"],
         "refine_ms": res["fp32_refine"]["ms"], "refine_inner_sweeps": res["fp32_refine"]["sweeps"],
         "refine_relres": res["fp32_refine"]["relres"],
@@ -281,7 +282,7 @@ def controls(B, W, torch, stream):
         res[name] = {"us_per_sweep": round(us, 3), "GBps": round(info["alg_bytes_per_sweep"] / us / 1e3, 1),
                      "pct_hbm_peak": round(100 * info["alg_bytes_per_sweep"] / us / 1e3 / HBM_PEAK_GBS, 2),
                      "halo_entries": int(info["halo_entries"]), "col_bytes": int(info["col_bytes"]), "n": s.n,
-                     "nnz": s.nnz}
+                     "nnz": s.nnz, "matrix_loads": "kept" if info["keep_matrix"] else "streamed"}
         B.jac_destroy(h)
     return res
 

@@ -96,8 +96,8 @@ typedef enum {
                                     parts of the band-row modes, subdomains of
                                     JAC_SUBSTRUCT), rows renumbered part by part */
     JAC_OPT_CACHE = 11       /* matrix loads of a sweep: 0 = auto (default: kept in
-                                the caches when one sweep streams at most 240 MiB,
-                                which the 256 MB Infinity Cache then holds across
+                                the caches when one sweep streams at most 256 MiB,
+                                which the Infinity Cache then holds across
                                 sweeps; else streamed with the nontemporal hint);
                                 1 = always kept; 2 = always streamed.  A batched
                                 solve decides on the bytes of the whole batch  */

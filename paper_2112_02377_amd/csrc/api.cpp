@@ -199,12 +199,13 @@ int64_t sweep_stream_bytes(int64_t slots, int colfmt, int32_t n, int nrhs, bool 
     return slots * (t + (colfmt == COL_GLOBAL32 ? 4 : 2)) + 3 * t * (int64_t)n * nrhs;
 }
 
-// Auto: a launch whose sweep streams at most kKeepBytes keeps its matrix in
-// the 256 MB Infinity Cache across sweeps; a larger one would only thrash it
-// and evict the x entries that are gathered again.
+// Auto: a launch whose sweep streams at most the Infinity Cache's 256 MiB
+// keeps its matrix there across sweeps; a larger one would only thrash it and
+// evict the x entries that are gathered again.  Measured on 7-point
+// Laplacians, the two kinds of load break even at about 267 MiB per sweep.
 int32_t keep_matrix(int32_t policy, int64_t bytes)
 {
-    constexpr int64_t kKeepBytes = 240ll << 20;
+    constexpr int64_t kKeepBytes = 256ll << 20;
     if (policy == 1) return 1;
     if (policy == 2) return 0;
     return bytes <= kKeepBytes ? 1 : 0;

@@ -11,7 +11,7 @@ from paper_2112_02377_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KEEP_BYTES = 240 << 20
+KEEP_BYTES = 256 << 20
 
 
 def streamed(info):
