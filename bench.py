@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--sweeps", type=int, default=2000)
     ap.add_argument("--modes", default="JB,JBO,JSS")
@@ -100,6 +100,26 @@ def cpu_baseline(sysm, seconds):
             "sample": f"{done} sweeps of the same {round(sysm.n ** (1 / 3))}^3 system from x0 = 0 in chunks of {chunk} "
                       f"(residual norm per sweep), plain C FP64 oracle, {threads} OpenMP threads, {dt:.1f} s",
             "sweeps_per_s": round(done / dt, 3)}
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy rate on this GPU (bytes read + written / time):
+    the plain-copy reference the sweep's traffic is compared with."""
+    a = torch.empty(mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = reps * 2 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, c
+    return round(gbs, 1)
 
 
 def _timed(torch, stream, fn):
@@ -524,6 +544,10 @@ def main():
            "roofline": roof, "modes": per_mode, "wall_s": round(wall, 3)}
     for h in handles.values():
         B.jac_destroy(h)
+    # the traffic the kernels stream (dev_GBps) beside a plain device copy's rate
+    out["copy_GBps"] = copy_bandwidth(torch)
+    for m in sel:
+        per_mode[m]["pct_of_copy"] = round(100 * per_mode[m]["dev_GBps"] / out["copy_GBps"], 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
     if not args.no_secondary:
