@@ -1,0 +1,120 @@
+"""GPU: edge cases of the sweep path through the C ABI.
+
+Tile shapes at their limits (64-row tiles, one tile for the whole system,
+more waves than slices), LDS too small to stage (the planner then sweeps
+unstaged), a one-row system, zero sweeps, maxit = 0, and the arguments the
+library rejects.  Iterates are bit-identical under every tile shape: each row
+accumulates its entries in the same order whatever the tiling; only the norm's
+summation order changes."""
+import numpy as np
+import pytest
+
+from gpu_util import B, get_x, make, need_gpu, rel_inf, set_x, sweep, torch
+from oracle import ref
+from paper_2112_02377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64), (64, 512), (128, 256), (1024, 512), (1 << 20, 256)]
+
+
+@pytest.mark.parametrize("mode,P,sub", [(1, 3, None), (2, 5, None), (3, 4, (2, 2, 1))])
+def test_tile_shapes_and_unstaged_fallback(mode, P, sub):
+    need_gpu()
+    b = B()
+    s = W.laplace7(13, workload=1)             # 2197 rows: ragged against every tile size
+    K = 7
+    _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    ref_x = None
+    cases = [dict(tile=t, block=k) for t, k in SHAPES] + [dict(tile=512, block=256, lds=64)]
+    for c in cases:
+        opts = {b.JAC_OPT_TILE_ROWS: c["tile"], b.JAC_OPT_BLOCK: c["block"]}
+        if "lds" in c:
+            opts[b.JAC_OPT_LDS_ELEMS] = c["lds"]
+        h = make(s, mode, P, sub, opts=opts)
+        info = b.jac_get_info(h)
+        if "lds" in c:
+            # no 64-row tile's footprint fits 64 entries: the whole plan is unstaged
+            assert info["staged_entries"] == 0 and info["max_footprint"] == 0
+        hist = sweep(h, K)[:, 0]
+        x = get_x(h, s.n)[0]
+        if ref_x is None:
+            ref_x = x
+        assert np.array_equal(x, ref_x), c
+        assert rel_inf(x, xr) <= 1e-12, c
+        assert np.all(np.abs(hist - hr) <= 1e-12 * hr), c
+        b.jac_set_x(h, None)                   # the solve continues from the handle's x
+        st, sw, rr = b.jac_solve(h, 1e-8, 5000)
+        sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-8, 5000)
+        assert int(sw[0]) == ko and rel_inf(get_x(h, s.n)[0], xo) <= 1e-10, c
+        b.jac_destroy(h)
+
+
+def test_one_row_system():
+    need_gpu()
+    b = B()
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    h = b.jac_create(1, rp, ci, np.array([4.0]), 1, np.array([3.0]))
+    hist = sweep(h, 2)[:, 0]
+    assert get_x(h, 1)[0][0] == 0.75                      # x_1 = b / a exactly
+    assert hist[0] == 3.0 and hist[1] == 0.0
+    b.jac_set_x(h, None)
+    st, sw, rr = b.jac_solve(h, 1e-12, 10)
+    sto, xo, ko, rro = ref.solve(rp, ci, np.array([4.0]), np.array([3.0]), 1e-12, 10)
+    assert st == b.JAC_OK and int(sw[0]) == ko == 1 and rr[0] == rro == 0.0
+    b.jac_destroy(h)
+
+
+def test_zero_sweeps_and_zero_maxit():
+    need_gpu()
+    b = B()
+    s = W.laplace7(7, workload=1)
+    h = make(s, 2, 3)
+    x0 = np.random.default_rng(3).uniform(-1, 1, s.n)
+    set_x(h, x0)
+    b.jac_sweep(h, 0)
+    assert np.array_equal(get_x(h, s.n)[0], x0)
+    b.jac_set_x(h, None)
+    st, sw, rr = b.jac_solve(h, 1e-30, 0)
+    sto, xo, ko, rro = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-30, 0)
+    assert st == b.JAC_NOT_CONVERGED == sto and int(sw[0]) == ko == 0
+    assert np.all(get_x(h, s.n)[0] == 0.0) and abs(rr[0] - rro) <= 1e-15
+    b.jac_destroy(h)
+
+
+def test_rejected_arguments():
+    need_gpu()
+    b = B()
+    rp = np.array([0, 1, 2], np.int32)
+    ci = np.array([0, 1], np.int32)
+    v = np.array([2.0, 2.0])
+    with pytest.raises(b.JacError) as e:
+        b.jac_create(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), 1, np.zeros(0))
+    assert e.value.status == b.JAC_E_INVALID
+    with pytest.raises(b.JacError) as e:
+        b.jac_create(2, rp, ci, v, 3, np.ones(6))
+    assert e.value.status == b.JAC_E_INVALID
+    h = b.jac_create(2, rp, ci, v, 1, np.ones(2))
+    for mode, P, sub in ((1, 3, None), (2, 0, None), (3, 2, (1, 1, 1)), (7, 1, None)):
+        with pytest.raises(b.JacError) as e:
+            b.jac_partition(h, mode, P, sub)
+        assert e.value.status == b.JAC_E_INVALID, (mode, P, sub)
+    for opt, val in ((b.JAC_OPT_TILE_ROWS, 100), (b.JAC_OPT_BLOCK, 1024), (b.JAC_OPT_LDS_ELEMS, 10),
+                     (b.JAC_OPT_LOOP, 2), (b.JAC_OPT_TIMING, 5)):
+        with pytest.raises(b.JacError) as e:
+            b.jac_set_option(h, opt, val)
+        assert e.value.status == b.JAC_E_INVALID, opt
+    with pytest.raises(b.JacError) as e:
+        b.jac_sweep(h, -1)
+    assert e.value.status == b.JAC_E_INVALID
+    with pytest.raises(b.JacError) as e:
+        b.jac_solve(h, -1.0, 10)
+    assert e.value.status == b.JAC_E_INVALID
+    with pytest.raises(b.JacError) as e:
+        b.jac_set_grid(h, 3, 1, 1)
+    assert e.value.status == b.JAC_E_INVALID
+    # the handle still works after every rejected call
+    st, sw, rr = b.jac_solve(h, 1e-12, 10)
+    assert st == b.JAC_OK and np.array_equal(get_x(h, 2)[0], np.array([0.5, 0.5]))
+    b.jac_destroy(h)
