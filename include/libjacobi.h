@@ -100,7 +100,9 @@ typedef enum {
                                 which the Infinity Cache then holds across
                                 sweeps; else streamed with the nontemporal hint);
                                 1 = always kept; 2 = always streamed.  A batched
-                                solve decides on the bytes of the whole batch  */
+                                solve decides on the bytes of the systems still
+                                running (per-sweep launches: again whenever a
+                                system stops; persistent launch: once)         */
 } jac_option;
 
 typedef struct {

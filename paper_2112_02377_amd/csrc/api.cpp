@@ -288,7 +288,7 @@ int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 // Solve mode: stop tests up to kend = maxit.  States are initialised here.
 void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
               DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
-              int fp_bytes, int runs, int colfmt, int nrhs)
+              int fp_bytes, int runs, int colfmt, int nrhs, const std::vector<int64_t>* sys_bytes)
 {
     const int nsys = (int)sys.size();
     hipStream_t st = h.stream;
@@ -331,7 +331,17 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         // waits for it) and drops stopped systems from the list; a stopped
         // system still on the list costs its tiles an early return.
         if (!solve) fail(JAC_E_INVALID, "several systems are swept in solve mode only");
-        void* fn = sweep_kernel(fp32, nrhs, colfmt, 2, keep);
+        // the cache choice follows the systems still running: once their
+        // matrices fit the Infinity Cache, the launches keep them there
+        auto kernel_for = [&](const std::vector<int32_t>& running) {
+            bool kp = keep;
+            if (sys_bytes) {
+                int64_t by = 0;
+                for (int32_t s : running) by += (*sys_bytes)[(size_t)s];
+                kp = keep_matrix(h.opt.cache, by) != 0;
+            }
+            return sweep_kernel(fp32, nrhs, colfmt, 2, kp);
+        };
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
         const size_t wl_ints = 2 * (size_t)nsys + 1;
         const size_t host_bytes = (size_t)nsys * sizeof(SysState) + 2 * wl_ints * sizeof(int32_t);
@@ -367,6 +377,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         for (int32_t s = 0; s < nsys; ++s)
             if (tile_base[s + 1] > tile_base[s]) act.push_back(s);
         int32_t items = upload(act);
+        void* fn = kernel_for(act);
         h.last_grid = items + (int)act.size();
         const int chunk = 64;
         int32_t k = 0;
@@ -387,6 +398,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
                 if (next.size() != act.size()) {
                     act.swap(next);
                     items = upload(act);
+                    fn = kernel_for(act);
                 }
             }
             JAC_HIP(hipMemcpyAsync(states, d_state.p, (size_t)nsys * sizeof(SysState), hipMemcpyDeviceToHost, st));
@@ -736,14 +748,17 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
             fpb = std::max(fpb, h.lds_fp_bytes(false));
             runs = std::max(runs, h.lds_runs());
         }
-        // every sweep of the batch streams all its systems: one cache choice
-        int64_t bytes = 0;
-        for (int32_t s = 0; s < nsys; ++s) bytes += hs[s]->stream_bytes(false);
-        for (SysDev& d : sys) d.keep = keep_matrix(h0.opt.cache, bytes);
+        // a sweep of the batch streams every running system: the persistent
+        // launch decides once on the whole batch, the per-sweep launches
+        // again whenever systems leave the list
+        std::vector<int64_t> bytes((size_t)nsys);
+        int64_t total = 0;
+        for (int32_t s = 0; s < nsys; ++s) total += bytes[(size_t)s] = hs[s]->stream_bytes(false);
+        for (SysDev& d : sys) d.keep = keep_matrix(h0.opt.cache, total);
         for (int32_t s = 1; s < nsys; ++s) hs[s]->sync();
         upload(h0.d.batch_tile_base, tb, h0.stream);
         run_loop(h0, sys, false, true, maxit, 0, nullptr, h0.d.batch_sys, h0.d.batch_state, h0.d.batch_tile_base, tb,
-                 fpb, runs, colfmt, nrhs);
+                 fpb, runs, colfmt, nrhs, &bytes);
         std::vector<SysState> st((size_t)nsys);
         JAC_HIP(hipMemcpyAsync(st.data(), h0.d.batch_state.p, st.size() * sizeof(SysState), hipMemcpyDeviceToHost,
                                h0.stream));

@@ -123,7 +123,7 @@ struct Handle {
 int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work);
 void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
               DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
-              int fp_bytes, int runs, int colfmt, int nrhs);
+              int fp_bytes, int runs, int colfmt, int nrhs, const std::vector<int64_t>* sys_bytes = nullptr);
 jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t* sweeps_out, double* relres_out);
 void set_last_error(const std::string& m);
 
