@@ -15,11 +15,17 @@ parts under each split, the bench's default tile shape and loop:
   the Jacobi matrix has infinity norm 1, so after K sweeps the bound is
   K * 50 eps max(1, max|x|);
 * the 192^3 control, whose band reaches past 16-bit row offsets (32-bit
-  columns), a few sweeps against the oracle under the same bound."""
+  columns), a few sweeps against the oracle under the same bound;
+* the 96^3 27-point FE-like system of the refinement comparison: FP64 and
+  FP32-inner solves to 1e-10 against the oracle's FP64 solve;
+* the 256-system, 4-right-hand-side batch of the batched comparison: every
+  column against its system solved alone, and 8 systems against the oracle
+  column by column."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
-from gpu_util import B, get_x, make, need_gpu, sweep
+from gpu_util import B, get_x, make, need_gpu, rel_inf, sweep
 from oracle import ref
 from paper_2112_02377_amd import workloads as W
 
@@ -102,3 +108,55 @@ def test_192_control_uses_32_bit_columns():
     bound = K * 50 * EPS * max(1.0, np.abs(xr).max())
     assert np.abs(x - xr).max() <= bound
     assert np.all(np.abs(hist - hr) <= 1e-12 * hr + np.sqrt(s.n) * 12 * bound)
+
+
+def test_fe27_96_fp64_and_fp32_refinement_at_full_size():
+    # FP64: the oracle's stop sweep and iterate.  FP32 inner sweeps: the FP64
+    # residual of the returned x (recomputed here) meets the tolerance, and x
+    # lies within 1e-9 of the oracle's solution (both residuals are below
+    # 1e-10 ||b|| and ||A^-1|| is small for a 1.05-dominant matrix).
+    need_gpu()
+    b = B()
+    s = W.fe27(96, workload=3)
+    h = make(s, 1, 64)
+    st, sw, rr = b.jac_solve(h, 1e-10, 100000)
+    x64 = get_x(h, s.n)[0]
+    sto, xo, ko, rro = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-10, 100000, threads=16)
+    assert st == b.JAC_OK and sto == ref.OK and int(sw[0]) == ko
+    assert rel_inf(x64, xo) <= 1e-10
+    b.jac_set_x(h, None)
+    st, sw, rr = b.jac_solve(h, 1e-10, 100000, b.JAC_NORM_L2_REL, b.JAC_FP32_REFINE)
+    x = get_x(h, s.n)[0]
+    b.jac_destroy(h)
+    assert st == b.JAC_OK
+    A = sp.csr_matrix((s.vals, s.col_idx, s.row_ptr), shape=(s.n, s.n))
+    assert np.linalg.norm(s.b[0] - A @ x) / np.linalg.norm(s.b[0]) <= 1e-10 * 1.001
+    assert np.abs(x - xo).max() / np.abs(xo).max() <= 1e-9
+
+
+def test_full_batch_against_separate_solves_and_oracle():
+    # the 256 uneven diffusion systems (edges U[16,64]) x 4 right-hand sides
+    need_gpu()
+    b = B()
+    systems = W.diffusion_batch()
+    assert len(systems) == 256 and all(s.nrhs == 4 for s in systems)
+    hs = [make(s, 1, 1) for s in systems]
+    st, sw, rr = b.jac_solve_batched(hs, 1e-8, 100000)
+    assert st == b.JAC_OK
+    sizes = np.array([s.n for s in systems])
+    rng = np.random.default_rng(2112)
+    pick = sorted({int(sizes.argmin()), int(sizes.argmax())} | set(rng.choice(256, 6, replace=False).tolist()))
+    xb = {si: get_x(hs[si], systems[si].n, 4) for si in pick}
+    for h in hs:
+        b.jac_destroy(h)
+    for si in pick:
+        s = systems[si]
+        h = make(s, 1, 1)
+        st1, sw1, rr1 = b.jac_solve(h, 1e-8, 100000)
+        x1 = get_x(h, s.n, 4)
+        b.jac_destroy(h)
+        assert np.array_equal(sw[si], sw1) and np.array_equal(xb[si], x1), si
+        for c in range(4):
+            sto, xo, ko, rro = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[c], 1e-8, 100000, threads=16)
+            assert sto == ref.OK and sw[si, c] == ko, (si, c)
+            assert rel_inf(xb[si][c], xo) <= 1e-10, (si, c)
