@@ -50,7 +50,9 @@ typedef enum {
     JAC_E_ZERO_DIAG = -2,    /* a row lacks its diagonal or the diagonal is 0      */
     JAC_E_NOMEM = -3,        /* host or device allocation failed                   */
     JAC_E_HIP = -4,          /* HIP runtime error; the handle may be unusable      */
-    JAC_E_STATE = -5,        /* call made in the wrong order                       */
+    JAC_E_STATE = -5,        /* the handle has no usable split: a rebuild of it
+                                (jac_partition, jac_autotune) failed part-way;
+                                only a successful jac_partition clears this    */
     JAC_E_DIVERGED = -6      /* residual norm non-finite or beyond 1e150*max(|b|,1) */
 } jac_status;
 
@@ -164,7 +166,12 @@ jac_status jac_set_grid(jac_handle h, int32_t nx, int32_t ny, int32_t nz);
  * a neighbour in A or A^T lies in another subdomain; the new order is the
  * interiors of each subdomain (ascending original index) then the interface
  * sorted by (subdomain, index) (section 4.3, block form with interface last).
- * Rebuilds the device layout and resets x to the current x in the new order. */
+ * Rebuilds the device layout and resets x to the current x in the new order.
+ * Arguments are checked before anything changes (JAC_E_INVALID leaves the
+ * handle as it was); a failure while the device layout is being replaced
+ * (JAC_E_NOMEM, JAC_E_HIP) leaves the handle unusable (JAC_E_STATE from
+ * every call that needs the layout) until a jac_partition succeeds, with x
+ * then restarting from 0. */
 jac_status jac_partition(jac_handle h, jac_mode mode, int32_t nparts, const int32_t *sub_grid_host);
 
 /* Host copies of the split, for inspection and parity checks.  Any output

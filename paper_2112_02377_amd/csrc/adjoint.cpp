@@ -152,6 +152,7 @@ extern "C" jac_status jac_sweep_checkpointed(jac_handle hp, int32_t K, int32_t c
 {
     return guarded([&]() -> jac_status {
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
+        hp->require_plan();
         Handle& h = *hp;
         if (K < 0 || ckpt_every < 1) fail(JAC_E_INVALID, "need K >= 0 and ckpt_every >= 1");
         if (h.nrhs != 1) fail(JAC_E_INVALID, "checkpointed sweeps need a handle with one right-hand side");
@@ -168,6 +169,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
 {
     return guarded([&]() -> jac_status {
         if (!hp || !gx_dev) fail(JAC_E_INVALID, "NULL argument");
+        hp->require_plan();
         Handle& h = *hp;
         if (K < 0 || ckpt < 1) fail(JAC_E_INVALID, "need K >= 0 and ckpt_every >= 1");
         if (h.nrhs != 1) fail(JAC_E_INVALID, "jac_adjoint needs a handle with one right-hand side");

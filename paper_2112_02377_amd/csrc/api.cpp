@@ -61,6 +61,11 @@ static void upload(DevMem& m, const std::vector<V>& v, hipStream_t st)
 
 void Handle::sync() { JAC_HIP(hipStreamSynchronize(stream)); }
 
+void Handle::require_plan() const
+{
+    if (!planned) fail(JAC_E_STATE, "the handle has no usable split (a rebuild failed); call jac_partition again");
+}
+
 Handle::~Handle()
 {
     for (auto& e : ev)
@@ -91,6 +96,9 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     for (size_t q = 0; q < src.size(); ++q) slot_of_caller[src[q]] = (int32_t)pl.slot_of_nnz[q];
     std::vector<int32_t> diag32(pl.diag_slot.begin(), pl.diag_slot.end());
     sync();
+    // from here on the device arrays are replaced one by one: the handle is
+    // unusable until the end (an exception leaves it so)
+    planned = false;
     part = std::move(np);
     plan = std::move(pl);
     part_mode = mode;
@@ -135,7 +143,6 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     d.tile_part.alloc(2 * (size_t)std::max(plan.ntiles, 1) * nrhs * sizeof(double));
     std::vector<int32_t> tb = {0, plan.ntiles};
     upload(d.tile_base, tb, stream);
-    planned = true;
     apply_values();
     launch_gather_in(static_cast<const double*>(d.b_caller.p), static_cast<const int32_t*>(d.perm.p), a.n, nrhs,
                      static_cast<double*>(d.b.p), stream);
@@ -143,6 +150,7 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
                      a.n, nrhs, static_cast<double*>(d.x0.p), stream);
     update_bnorm();
     sync();
+    planned = true;
 }
 
 // Caller-order values (device copy) -> slots, D^{-1}, FP32 copies if used.
@@ -526,6 +534,7 @@ jac_status jac_set_values(jac_handle h, const double* vals_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h || !vals_dev) fail(JAC_E_INVALID, "NULL argument");
+        h->require_plan();
         ++h->state_gen;
         DevMem old;
         old.alloc((size_t)h->a.nnz() * sizeof(double));
@@ -549,6 +558,7 @@ jac_status jac_set_rhs(jac_handle h, const double* b_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h || !b_dev) fail(JAC_E_INVALID, "NULL argument");
+        h->require_plan();
         ++h->state_gen;
         JAC_HIP(hipMemcpyAsync(h->d.b_caller.p, b_dev, (size_t)h->a.n * h->nrhs * sizeof(double),
                                hipMemcpyDeviceToDevice, h->stream));
@@ -585,6 +595,7 @@ jac_status jac_get_partition(jac_handle h, int32_t* perm, int32_t* bounds, int32
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        h->require_plan();
         const Partition& p = h->part;
         if (bounds && (!nbounds || *nbounds < (int32_t)p.bounds.size())) fail(JAC_E_INVALID, "bounds too small");
         if (recv_idx && (!nrecv || *nrecv < (int64_t)p.recv_idx.size())) fail(JAC_E_INVALID, "recv_idx too small");
@@ -602,6 +613,7 @@ jac_status jac_get_send_lists(jac_handle h, int32_t* send_ptr, int32_t* send_des
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        h->require_plan();
         const Partition& p = h->part;
         const int32_t P = p.nparts;
         const size_t m = p.recv_idx.size();
@@ -636,6 +648,7 @@ jac_status jac_set_x(jac_handle h, const double* x_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        h->require_plan();
         ++h->state_gen;
         launch_gather_in(x_dev, static_cast<const int32_t*>(h->d.perm.p), h->a.n, h->nrhs,
                          static_cast<double*>(h->d.x0.p), h->stream);
@@ -647,6 +660,7 @@ jac_status jac_get_x(jac_handle h, double* x_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h || !x_dev) fail(JAC_E_INVALID, "NULL argument");
+        h->require_plan();
         h->get_x_dev(x_dev);
         return JAC_OK;
     });
@@ -656,6 +670,7 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double* hist_dev)
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        h->require_plan();
         if (nsweeps < 0) fail(JAC_E_INVALID, "nsweeps must be >= 0");
         if (nsweeps == 0) return JAC_OK;
         ++h->state_gen;
@@ -706,6 +721,7 @@ jac_status jac_solve(jac_handle h, double tol, int32_t maxit, jac_norm norm, jac
 {
     return guarded([&]() -> jac_status {
         if (!h) fail(JAC_E_INVALID, "NULL handle");
+        h->require_plan();
         if (!(tol >= 0.0) || maxit < 0) fail(JAC_E_INVALID, "tol must be >= 0 and maxit >= 0");
         if (norm != JAC_NORM_L2_REL && norm != JAC_NORM_INF_ABS) fail(JAC_E_INVALID, "bad norm");
         ++h->state_gen;
@@ -730,8 +746,9 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         std::vector<double> scale((size_t)nsys * 4, 1.0);
         int fpb = 0, runs = 0;
         for (int32_t s = 0; s < nsys; ++s) {
-            Handle& h = *hs[s];
             if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
+            hs[s]->require_plan();
+            Handle& h = *hs[s];
             if (h.nrhs != nrhs || h.plan.colfmt != colfmt)
                 fail(JAC_E_INVALID, "all handles of a batch need the same nrhs and column format");
             if (h.device != h0.device) fail(JAC_E_INVALID, "all handles of a batch must be on one device");

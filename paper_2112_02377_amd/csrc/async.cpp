@@ -27,6 +27,7 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
 {
     return guarded([&]() -> jac_status {
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
+        hp->require_plan();
         if (!(tol >= 0.0) || maxit < 0) fail(JAC_E_INVALID, "tol must be >= 0 and maxit >= 0");
         if (norm != JAC_NORM_L2_REL && norm != JAC_NORM_INF_ABS) fail(JAC_E_INVALID, "bad norm");
         if (rounds_per_check < 1) fail(JAC_E_INVALID, "rounds_per_check must be >= 1");

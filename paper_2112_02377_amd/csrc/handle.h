@@ -116,6 +116,11 @@ struct Handle {
     void settle(uint32_t which);
     SysDev sysdev(bool fp32) const;
     int64_t stream_bytes(bool fp32) const;
+    // Entry points that use the device arrays call this first: a rebuild of
+    // the split that failed part-way (out of device memory, say) leaves
+    // arrays that no longer match the plan, and nothing may launch on them
+    // until a jac_partition succeeds.
+    void require_plan() const;
     int lds_fp_bytes(bool fp32) const;
     int lds_runs() const;
 };

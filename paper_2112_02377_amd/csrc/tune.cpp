@@ -87,6 +87,7 @@ extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
 {
     return guarded([&]() -> jac_status {
         if (!hp) fail(JAC_E_INVALID, "NULL handle");
+        hp->require_plan();
         if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
         Handle& h = *hp;
         ++h.state_gen;
@@ -140,8 +141,10 @@ extern "C" jac_status jac_autotune_batched(const jac_handle* hs, int32_t nsys, i
     return guarded([&]() -> jac_status {
         if (!hs || nsys < 1) fail(JAC_E_INVALID, "need at least one handle");
         if (sweeps_per_trial < 1) fail(JAC_E_INVALID, "sweeps_per_trial must be >= 1");
-        for (int32_t s = 0; s < nsys; ++s)
+        for (int32_t s = 0; s < nsys; ++s) {
             if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
+            hs[s]->require_plan();
+        }
         for (int32_t s = 0; s < nsys; ++s) ++hs[s]->state_gen;
         static const Cand kBatch[] = {{256, 256}, {512, 256}, {1024, 256}, {2048, 256}};
         Handle& h0 = *hs[0];
