@@ -143,8 +143,8 @@ def sweep_rows(row_ptr, col_idx, vals, b, x, rows):
 
 def batched_solve(systems, tol: float, maxit: int, threads: int = 1):
     """Reference for many systems with several right-hand sides: one plain
-    solve per (system, right-hand side).  Returns lists of (status, x, sweeps,
-    relres) per system, each an array over right-hand sides."""
+    solve per (system, right-hand side).  Returns, per system, a list over its
+    right-hand sides of (status, x, sweeps, relres)."""
     out = []
     for s in systems:
         res = [solve(s.row_ptr, s.col_idx, s.vals, s.b[c], tol, maxit, NORM_L2_REL, threads=threads)

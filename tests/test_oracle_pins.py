@@ -175,3 +175,29 @@ def test_sweep_rows_matches_full_sweep():
     rows = np.array([0, 7, 63, 100, 511])
     st, out, _ = ref.sweep_rows(s.row_ptr, s.col_idx, s.vals, s.b[0], x5, rows)
     assert st == ref.OK and np.array_equal(out, x6[rows])
+
+
+def test_batched_reference_against_an_independent_jacobi():
+    # each (system, right-hand side) column: the sweep count is the first k
+    # whose residual meets the relative test, with x_k and the residuals
+    # recomputed by a separate numpy/scipy Jacobi iteration
+    import scipy.sparse as sp
+    systems = W.diffusion_batch(3, workload=4, lo=4, hi=7)
+    out = ref.batched_solve(systems, 1e-8, 100000)
+    assert len(out) == 3
+    for s, res in zip(systems, out):
+        A = sp.csr_matrix((s.vals, s.col_idx, s.row_ptr), shape=(s.n, s.n))
+        d = A.diagonal()
+        assert len(res) == s.b.shape[0] == 4
+        for c, (st, x, k, rel) in enumerate(res):
+            b = s.b[c]
+            nb = np.linalg.norm(b)
+            xs, prev = np.zeros(s.n), None
+            for _ in range(k):
+                prev = xs
+                xs = xs + (b - A @ xs) / d
+            assert st == ref.OK
+            assert np.abs(x - xs).max() <= 1e-12 * max(1.0, np.abs(xs).max())
+            r_k = np.linalg.norm(b - A @ xs) / nb
+            assert r_k <= 1e-8 * (1 + 1e-9) and abs(rel - r_k) <= 1e-6 * r_k
+            assert np.linalg.norm(b - A @ prev) / nb > 1e-8 * (1 - 1e-9)
