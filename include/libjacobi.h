@@ -85,7 +85,8 @@ typedef enum {
     JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU (0 = occupancy)  */
     JAC_OPT_INNER_TOL = 6,   /* FP32 refinement: inner relative residual, x1e-9     */
     JAC_OPT_INNER_MAX = 7,   /* FP32 refinement: max inner sweeps per outer step    */
-    JAC_OPT_CKPT_MEM_MB = 8, /* adjoint: cap on segment buffers (MiB)               */
+    JAC_OPT_CKPT_MEM_MB = 8, /* adjoint: cap on its device buffers (MiB), default
+                                4096; all iterates are stored when they fit    */
     JAC_OPT_TIMING = 9,      /* 1 = time each sweep loop with HIP events on the
                                 handle's stream (jac_info.last_loop_ms); the call
                                 then waits for the loop to finish                  */
@@ -252,9 +253,10 @@ jac_status jac_solve_async(jac_handle h, double tol, int32_t maxit, jac_norm nor
                            int32_t *rounds_out, double *relres_out);
 
 /* K sweeps from x_0 = 0 for right-hand side 0 (like jac_set_x(NULL) then
- * jac_sweep(K)), keeping the iterates x_{j*ckpt_every} on the device as the
- * checkpoints of a later jac_adjoint with the same K and stride, which then
- * skips its own forward pass.  The checkpoints stay valid until a call
+ * jac_sweep(K)), keeping iterates on the device for a later jac_adjoint with
+ * the same K and stride, which then skips its own forward pass: all of
+ * x_0 .. x_K when they fit JAC_OPT_CKPT_MEM_MB (see jac_adjoint), else the
+ * checkpoints x_{j*ckpt_every}.  The checkpoints stay valid until a call
  * changes the system, its split or x (jac_info.state_gen).  Leaves x_K in the
  * handle. */
 jac_status jac_sweep_checkpointed(jac_handle h, int32_t K, int32_t ckpt_every);
@@ -262,13 +264,16 @@ jac_status jac_sweep_checkpointed(jac_handle h, int32_t K, int32_t ckpt_every);
 /* Reverse-mode derivative of K sweeps from x_0 = 0 for right-hand side 0:
  * given gx_dev = dL/dx_K (n, original order), writes gb_dev = dL/db (n) and
  * gvals_dev = dL/dvals (nnz, caller's CSR entry order, diagonal included).
- * Iterates are checkpointed every ckpt_every sweeps and recomputed per
- * segment; the forward pass that takes the checkpoints is skipped when
- * jac_sweep_checkpointed left valid ones for this K and stride.  Leaves
- * x = x_K in the handle.  Either output may be NULL.
- * Device memory: ceil(K/ckpt_every) + 2*ckpt_every + 5 vectors of n doubles plus
- * one double per stored slot (at most JAC_OPT_CKPT_MEM_MB, else
- * JAC_E_INVALID), kept by the handle for later calls until jac_destroy. */
+ * The reverse pass runs in segments of ckpt_every sweeps.  When
+ * K + 1 + ckpt_every + 4 vectors of n doubles, one double per stored slot and
+ * K sweep descriptors fit JAC_OPT_CKPT_MEM_MB, the forward stores every
+ * iterate and nothing is recomputed; otherwise it keeps every
+ * ckpt_every-th iterate (ceil(K/ckpt_every) + 2*ckpt_every + 5 vectors plus
+ * one double per slot, else JAC_E_INVALID) and each segment is swept again
+ * from its checkpoint.  Both give bit-identical results.  The forward pass
+ * is skipped when jac_sweep_checkpointed left valid iterates for this K and
+ * stride.  Leaves x = x_K in the handle.  Either output may be NULL.  The
+ * buffers stay with the handle for later calls until jac_destroy. */
 jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double *gx_dev, double *gb_dev,
                        double *gvals_dev);
 

@@ -7,11 +7,15 @@
 //   dL/db    += mu_{k+1}
 //   dL/da_ij -= mu_{k+1,i} x_{k,j}      (j != i)
 //   dL/da_ii -= mu_{k+1,i} x_{k+1,i}    (through both A x_k and 1/a_ii)
-// The iterates are kept only every ckpt_every sweeps.  Each segment is swept
-// again from its checkpoint with the same kernel (bit-identical iterates; its
-// last iterate is the next checkpoint and is copied, not recomputed), then
-// reversed step by step on A^T, and its dL/dvals contributions are added in
-// one pass over A's stored entries.  The forward and the reverse queue all
+// The reverse pass runs in segments of ckpt_every sweeps.  When all K + 1
+// iterates fit the checkpoint memory cap, the forward writes every one of
+// them (each sweep straight into its slot) and a segment reads its iterates
+// from there; otherwise only every ckpt_every-th iterate is kept and each
+// segment is swept again from its checkpoint with the same kernel
+// (bit-identical iterates; its last iterate is the next checkpoint and is
+// copied, not recomputed).  A segment is then reversed step by step on A^T,
+// and its dL/dvals contributions are added in one pass over A's stored
+// entries.  The forward and the reverse queue all
 // their launches without waiting for the device; the working buffers stay
 // with the handle for the next call.
 #include <algorithm>
@@ -93,28 +97,83 @@ static void build_transpose(Handle& h)
 // the adjoint's buffers.
 static int32_t ckpt_stride(int32_t K, int32_t ckpt) { return std::max(1, std::min(ckpt, std::max(K, 1))); }
 
-static void check_adjoint_memory(const Handle& h, int32_t K, int32_t c)
+// Device bytes of the adjoint's buffers for K sweeps in segments of c: the
+// stored iterates (all K + 1, or every c-th), per segment the mu vectors (and,
+// when iterates are recomputed, the c + 1 iterates), four vectors, the
+// gradient accumulator, and the per-sweep descriptors of the forward.
+static size_t adjoint_bytes(const Handle& h, int32_t K, int32_t c, bool all)
 {
     const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
     const size_t vec = (size_t)h.a.n * sizeof(double);
-    const size_t need = (size_t)nseg * vec + (size_t)(2 * c + 1) * vec + 4 * vec + (size_t)h.plan.slots * 8;
-    if (need > (size_t)h.opt.ckpt_mb << 20)
+    const size_t stored = all ? (size_t)(K + 1) * vec : (size_t)nseg * vec;
+    const size_t seg = all ? (size_t)c * vec : (size_t)(2 * c + 1) * vec;
+    const size_t desc = all ? (size_t)std::max(K, 1) * sizeof(SysDev) : 0;
+    return stored + seg + 4 * vec + (size_t)h.plan.slots * 8 + desc;
+}
+
+static bool store_all(const Handle& h, int32_t K, int32_t c)
+{
+    return adjoint_bytes(h, K, c, true) <= ((size_t)h.opt.ckpt_mb << 20);
+}
+
+static void check_adjoint_memory(const Handle& h, int32_t K, int32_t c)
+{
+    if (!store_all(h, K, c) && adjoint_bytes(h, K, c, false) > ((size_t)h.opt.ckpt_mb << 20))
         fail(JAC_E_INVALID, "adjoint buffers exceed JAC_OPT_CKPT_MEM_MB; raise it or the checkpoint stride");
 }
 
-// K sweeps from x_0 = 0, one launch per sweep on the handle's three iterate
-// buffers (x_k in buffer k mod 3), x_{jc} copied out as checkpoint j.  Ends
-// with x_K in the handle's first buffer and the checkpoints marked valid for
-// the handle's current state.
+// K sweeps from x_0 = 0, one launch per sweep.  All iterates stored: sweep k
+// reads slot k and writes slot k + 1 of the checkpoint buffer (a descriptor
+// per sweep).  Otherwise the handle's three iterate buffers (x_k in buffer
+// k mod 3) with x_{jc} copied out as checkpoint j.  Ends with x_K in the
+// handle's first buffer and the checkpoints marked valid for the handle's
+// current state.
 static void forward_ckpt(Handle& h, int32_t K, int32_t c)
 {
     const int32_t n = h.a.n;
     const hipStream_t st = h.stream;
     const int32_t nseg = K > 0 ? (K + c - 1) / c : 0;
     const size_t vec = (size_t)n * sizeof(double);
+    const bool all = store_all(h, K, c);
     DeviceArrays& d = h.d;
-    d.adj_ck.ensure(std::max<size_t>((size_t)nseg * vec, 16));
+    d.adj_ck.ensure(std::max<size_t>((all ? (size_t)(K + 1) : (size_t)nseg) * vec, 16));
     const SysDev sA = h.sysdev(false);
+    if (all) {
+        auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
+        std::vector<SysDev> fs((size_t)std::max(K, 1), sA);
+        for (int32_t k = 0; k < K; ++k) {
+            fs[k].x[0] = CK(k);
+            fs[k].x[1] = CK(k + 1);
+            fs[k].x[2] = CK(k + 1);
+        }
+        d.adj_fsegs.ensure(sizeof(SysDev) * fs.size());
+        JAC_HIP(hipMemcpyAsync(d.adj_fsegs.p, fs.data(), sizeof(SysDev) * fs.size(), hipMemcpyHostToDevice, st));
+        d.state.ensure(sizeof(SysState));
+        JAC_HIP(hipStreamSynchronize(st));   // fs is a temporary
+        void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
+        const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
+        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const int grid = std::max(h.plan.ntiles, 1) + 1;
+        launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, CK(0), st);
+        launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
+        for (int32_t k = 0; k < K; ++k) {
+            // sweep 0 of its own descriptor: reads x[0], writes x[1], decides nothing
+            LoopParams p{};
+            p.sys = static_cast<const SysDev*>(d.adj_fsegs.p) + k;
+            p.st = static_cast<SysState*>(d.state.p);
+            p.nsys = 1;
+            p.k0 = 0;
+            p.kend = 1;
+            p.solve = 0;
+            launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, runs);
+        }
+        JAC_HIP(hipMemcpyAsync(d.x0.p, CK(K), vec, hipMemcpyDeviceToDevice, st));
+        h.ckpt_K = K;
+        h.ckpt_c = c;
+        h.ckpt_all = true;
+        h.ckpt_gen = h.state_gen;
+        return;
+    }
     d.sys.ensure(sizeof(SysDev));
     JAC_HIP(hipMemcpyAsync(d.sys.p, &sA, sizeof(SysDev), hipMemcpyHostToDevice, st));
     d.state.ensure(sizeof(SysState));
@@ -141,6 +200,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
     h.settle((uint32_t)(K % 3));
     h.ckpt_K = K;
     h.ckpt_c = c;
+    h.ckpt_all = false;
     h.ckpt_gen = h.state_gen;
 }
 
@@ -209,19 +269,27 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
             desc[1].col32 = static_cast<const int32_t*>(h.td.a_gcol.p);
             gfmt = COL_GLOBAL32;
         }
+        // the forward with checkpoints, unless jac_sweep_checkpointed left
+        // them for this K and stride and nothing changed the handle since
+        const bool reuse = h.ckpt_gen == h.state_gen && h.ckpt_K == K && h.ckpt_c == c;
+        const bool all = reuse ? h.ckpt_all : store_all(h, K, c);
         // recompute sweeps: sweep m of a segment reads X[m] and writes X[m+1]
-        d.adj_X.ensure((size_t)(c + 1) * vec);
         auto Xm = [&](int m) { return static_cast<double*>(d.adj_X.p) + (size_t)m * n; };
-        std::vector<SysDev> segs((size_t)c, sA);
-        for (int32_t m = 0; m < c; ++m) {
-            segs[m].x[0] = Xm(m);
-            segs[m].x[1] = Xm(m + 1);
-            segs[m].x[2] = Xm(m + 1);
+        std::vector<SysDev> segs;
+        if (!all) {
+            d.adj_X.ensure((size_t)(c + 1) * vec);
+            segs.assign((size_t)c, sA);
+            for (int32_t m = 0; m < c; ++m) {
+                segs[m].x[0] = Xm(m);
+                segs[m].x[1] = Xm(m + 1);
+                segs[m].x[2] = Xm(m + 1);
+            }
+            d.adj_segs.ensure(sizeof(SysDev) * (size_t)c);
+            JAC_HIP(hipMemcpyAsync(d.adj_segs.p, segs.data(), sizeof(SysDev) * (size_t)c, hipMemcpyHostToDevice,
+                                   st));
         }
         d.adj_sys.ensure(sizeof(desc));
-        d.adj_segs.ensure(sizeof(SysDev) * (size_t)c);
         JAC_HIP(hipMemcpyAsync(d.adj_sys.p, desc, sizeof(desc), hipMemcpyHostToDevice, st));
-        JAC_HIP(hipMemcpyAsync(d.adj_segs.p, segs.data(), sizeof(SysDev) * (size_t)c, hipMemcpyHostToDevice, st));
         d.state.ensure(sizeof(SysState));
         JAC_HIP(hipStreamSynchronize(st));   // the host descriptors are temporaries
         const SysDev* d_sT = static_cast<const SysDev*>(d.adj_sys.p);
@@ -236,9 +304,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         JAC_HIP(hipMemsetAsync(d.adj_gb.p, 0, vec, st));
         auto Mm = [&](int m) { return static_cast<double*>(d.adj_M.p) + (size_t)m * n; };
         auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
-        // the forward with checkpoints, unless jac_sweep_checkpointed left
-        // them for this K and stride and nothing changed the handle since
-        if (!(h.ckpt_gen == h.state_gen && h.ckpt_K == K && h.ckpt_c == c)) {
+        if (!reuse) {
             ++h.state_gen;
             forward_ckpt(h, K, c);
         }
@@ -261,11 +327,14 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
             for (int32_t j = nseg - 1; j >= 0; --j) {
                 const int32_t k0 = j * c;
                 const int32_t L = std::min(c, K - k0);
-                // x_{k0} .. x_{k0+L}: both ends are known (checkpoints, or x_K
-                // from the forward), the sweeps in between are recomputed
-                JAC_HIP(hipMemcpyAsync(Xm(0), CK(j), vec, hipMemcpyDeviceToDevice, st));
-                JAC_HIP(hipMemcpyAsync(Xm(L), j + 1 < nseg ? CK(j + 1) : xK, vec, hipMemcpyDeviceToDevice, st));
-                for (int32_t m = 0; m + 1 < L; ++m) {
+                // x_{k0} .. x_{k0+L}: stored, or both ends known (checkpoints,
+                // or x_K from the forward) and the sweeps in between recomputed
+                const double* X0 = all ? CK(k0) : Xm(0);
+                if (!all) {
+                    JAC_HIP(hipMemcpyAsync(Xm(0), CK(j), vec, hipMemcpyDeviceToDevice, st));
+                    JAC_HIP(hipMemcpyAsync(Xm(L), j + 1 < nseg ? CK(j + 1) : xK, vec, hipMemcpyDeviceToDevice, st));
+                }
+                for (int32_t m = 0; !all && m + 1 < L; ++m) {
                     LoopParams p{};
                     p.sys = static_cast<const SysDev*>(d.adj_segs.p) + m;
                     p.st = static_cast<SysState*>(d.state.p);
@@ -283,7 +352,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                                     static_cast<double*>(d.adj_gb.p), static_cast<const double*>(d.invd.p));
                     std::swap(lin, lout);
                 }
-                launch_adj_grad(gfmt, h.plan.ntiles, st, d_sG, Xm(0), Mm(0), L, static_cast<double*>(d.adj_G.p));
+                launch_adj_grad(gfmt, h.plan.ntiles, st, d_sG, X0, Mm(0), L, static_cast<double*>(d.adj_G.p));
                 if (j > 0) JAC_HIP(hipMemcpyAsync(Mm(c - 1), d.adj_carry.p, vec, hipMemcpyDeviceToDevice, st));
             }
         }

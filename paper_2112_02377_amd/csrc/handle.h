@@ -66,7 +66,7 @@ struct DeviceArrays {
     // adjoint: A^T slot map, A's global columns (staged plans), and the
     // working buffers, kept between calls (grow-only)
     DevMem t_map, a_gcol;
-    DevMem adj_ck, adj_X, adj_M, adj_lam0, adj_lam1, adj_carry, adj_gb, adj_G, adj_sys, adj_segs;
+    DevMem adj_ck, adj_X, adj_M, adj_lam0, adj_lam1, adj_carry, adj_gb, adj_G, adj_sys, adj_segs, adj_fsegs;
     // asynchronous solve: descriptor, residual scratch, norms
     DevMem async_sys, async_r32, async_norm;
 };
@@ -104,6 +104,7 @@ struct Handle {
     int64_t state_gen = 1;
     int64_t ckpt_gen = 0;
     int32_t ckpt_K = -1, ckpt_c = 0;
+    bool ckpt_all = false;         // every iterate x_0..x_K stored (no recompute)
     Plan tplan;
     DeviceArrays td;
 

@@ -192,3 +192,48 @@ def test_autograd_backward_after_the_handle_was_used_again():
         grads.append(theta.grad.cpu().numpy())
     assert np.array_equal(grads[0], grads[1])
     b.jac_destroy(h)
+
+
+def test_stored_and_recomputed_iterates_give_identical_gradients():
+    # all K + 1 iterates fit the default cap: stored, nothing recomputed; a
+    # 1 MiB cap forces checkpoints every c sweeps and recomputed segments
+    need_gpu()
+    b = B()
+    s = W.diffusion_adjoint(10)
+    K, c = 300, 16
+    st, xo, _ = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    g = xo - s.extra["x_target"]
+    out = []
+    for cap in (4096, 1):
+        h = make(s, 2, 3, opts={b.JAC_OPT_CKPT_MEM_MB: cap})
+        gb, gv = run_adjoint(h, K, c, g, s.n, s.nnz)
+        out.append((gb, gv, get_x(h, s.n)[0]))
+        b.jac_destroy(h)
+    assert all(np.array_equal(u, v) for u, v in zip(out[0], out[1]))
+    sto, gbo, gvo, xk = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K, g)
+    assert np.abs(out[0][0] - gbo).max() <= 1e-10 * np.abs(gbo).max()
+    assert np.abs(out[0][1] - gvo).max() <= 1e-10 * np.abs(gvo).max()
+    assert rel_inf(out[0][2], xk) <= 1e-12
+    # a cap too small for either layout is refused
+    h = make(s, 1, 1, opts={b.JAC_OPT_CKPT_MEM_MB: 1})
+    with pytest.raises(b.JacError) as e:
+        b.jac_adjoint(h, 3000, 3000, dev(g), torch.empty(s.n, dtype=torch.float64, device="cuda"),
+                      torch.empty(s.nnz, dtype=torch.float64, device="cuda"))
+    assert e.value.status == b.JAC_E_INVALID
+    b.jac_destroy(h)
+
+
+def test_full_size_stored_and_recomputed_agree():
+    # 64^3, K = 400, segments of 20: 841 MB of iterates under the default cap
+    # against checkpoints every 20 sweeps under a 200 MiB cap
+    need_gpu()
+    b = B()
+    s = W.diffusion_adjoint(64)
+    g = np.random.default_rng(9).uniform(-1, 1, s.n)
+    res = []
+    for cap in (4096, 200):
+        h = make(s, 1, 1, opts={b.JAC_OPT_CKPT_MEM_MB: cap})
+        b.jac_sweep_checkpointed(h, 400, 20)
+        res.append(run_adjoint(h, 400, 20, g, s.n, s.nnz))
+        b.jac_destroy(h)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
