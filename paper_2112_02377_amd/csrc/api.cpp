@@ -270,14 +270,16 @@ int Handle::lds_fp_bytes(bool fp32) const
 
 int Handle::lds_runs() const { return plan.prm.staged ? std::max(plan.max_runs, 1) : 0; }
 
+// Compute units of the current device (queried once; the initialisation of a
+// function-local static is thread-safe, and retried if it throws).
 static int num_cus()
 {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
+    static const int cus = [] {
+        int dev = 0, n = 0;
         JAC_HIP(hipGetDevice(&dev));
-        JAC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    }
+        JAC_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        return n;
+    }();
     return cus;
 }
 
