@@ -531,7 +531,7 @@ def main():
     kern = {}
     for m in sel:
         kname = "k_loop" if args.loop else "k_sweep"
-        cm = 2 if m in ("JBO", "JSS") else (1 if infos[m]["col_bytes"] == 2 else 0)
+        cm = infos[m]["col_format"]
         nt = "false" if infos[m]["keep_matrix"] else "true"       # nontemporal matrix loads
         tag = f"{kname}<double, 1, {cm}, {nt}>"
         kern.setdefault(tag, []).append(m)
@@ -545,6 +545,16 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, bytes_launch),
             "kernel": dom, "modes": dm, "alg_bytes_per_launch": int(bytes_launch),
             "avg_launch_ms": round(avg_launch_ms, 5)}
+    # every sweep kernel of the step, the dominant one first
+    per_kernel = []
+    for t in sorted(kern, key=lambda t: -sum(per_mode[m]["loop_ms"] for m in kern[t])):
+        ms_l = sum(per_mode[m]["loop_ms"] for m in kern[t]) / len(kern[t]) / K
+        b_l = sum(alg[m] for m in kern[t]) / len(kern[t])
+        per_kernel.append({"kernel": t, "modes": kern[t], "avg_launch_ms": round(ms_l, 5),
+                           "achieved": round(b_l / (ms_l / 1e3) / 1e9, 1),
+                           "frac": round(b_l / (ms_l / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": traffic_from_profile(t, b_l)})
+    roof["kernels"] = per_kernel
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",

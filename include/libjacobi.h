@@ -98,7 +98,7 @@ typedef enum {
                                 2 = weighted graph partition (jac_graph_partition:
                                     parts of the band-row modes, subdomains of
                                     JAC_SUBSTRUCT), rows renumbered part by part */
-    JAC_OPT_CACHE = 11       /* matrix loads of a sweep: 0 = auto (default: kept in
+    JAC_OPT_CACHE = 11,      /* matrix loads of a sweep: 0 = auto (default: kept in
                                 the caches when one sweep streams at most 256 MiB,
                                 which the Infinity Cache then holds across
                                 sweeps; else streamed with the nontemporal hint);
@@ -106,6 +106,14 @@ typedef enum {
                                 solve decides on the bytes of the systems still
                                 running (per-sweep launches: again whenever a
                                 system stops; persistent launch: once)         */
+    JAC_OPT_SHIFT_TABLES = 12 /* 1 (default): when the slices of a split reach
+                                their columns through few distinct shifts
+                                (column minus row, or LDS position minus row
+                                for staged tiles; one per stencil neighbour),
+                                each slice stores its shifts once instead of a
+                                column per slot, if that streams fewer bytes
+                                over the whole split; 0: never.  Results are
+                                bit-identical either way                       */
 } jac_option;
 
 typedef struct {
@@ -114,7 +122,8 @@ typedef struct {
     int64_t ell_slots;           /* stored slots incl. padding (sliced layout)      */
     int32_t ntiles, nslices;
     int32_t max_footprint;       /* largest staged x footprint of a tile (entries)  */
-    int32_t col_bytes;           /* 4 = global int32 columns, 2 = tile-local u16    */
+    int32_t col_bytes;           /* bytes per column entry: 4 = global int32, 2 =
+                                    row-relative or tile-local, 0 = shift table    */
     int64_t halo_entries;        /* sum of the receive lists                        */
     int64_t staged_entries;      /* sum over tiles of staged x entries             */
     int64_t alg_bytes_per_sweep; /* 12 nnz + 4 (n+1) + 8 n + 24 n nrhs (CSR model)   */
@@ -127,6 +136,13 @@ typedef struct {
                                     with temporal hints (JAC_OPT_CACHE)              */
     int64_t state_gen;           /* raised by every call that changes the system, its
                                     split or x (checkpoints stay valid while it holds) */
+    int64_t table_slots;         /* slots when the split stores a table of column
+                                    shifts per slice instead of a column per slot
+                                    (JAC_OPT_SHIFT_TABLES), else 0                 */
+    int32_t col_format;          /* 0 global int32 columns, 1 row-relative int16,
+                                    2 tile-local uint16 (staged), 3 shift table,
+                                    4 shift table into the staged footprint        */
+    int32_t pad2_;
 } jac_info;
 
 /* Create a system from host CSR arrays (row_ptr[n+1], col_idx[nnz],

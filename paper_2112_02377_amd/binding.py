@@ -24,7 +24,8 @@ JAC_BANDROW, JAC_BANDROW_SP, JAC_SUBSTRUCT = 1, 2, 3
 JAC_NORM_L2_REL, JAC_NORM_INF_ABS = 0, 1
 JAC_FP64, JAC_FP32_REFINE = 0, 1
 (JAC_OPT_TILE_ROWS, JAC_OPT_BLOCK, JAC_OPT_LDS_ELEMS, JAC_OPT_LOOP, JAC_OPT_WG_PER_CU, JAC_OPT_INNER_TOL,
- JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING, JAC_OPT_PARTITIONER, JAC_OPT_CACHE) = range(1, 12)
+ JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING, JAC_OPT_PARTITIONER, JAC_OPT_CACHE,
+ JAC_OPT_SHIFT_TABLES) = range(1, 13)
 CACHE_AUTO, CACHE_KEEP, CACHE_STREAM = 0, 1, 2
 PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 
@@ -42,7 +43,8 @@ class jac_info(C.Structure):
                 ("staged_entries", C.c_int64), ("alg_bytes_per_sweep", C.c_int64),
                 ("dev_bytes_per_sweep", C.c_int64), ("loop_grid", C.c_int32), ("block", C.c_int32),
                 ("last_loop_ms", C.c_double), ("last_loop_sweeps", C.c_int32), ("keep_matrix", C.c_int32),
-                ("state_gen", C.c_int64)]
+                ("state_gen", C.c_int64), ("table_slots", C.c_int64),
+                ("col_format", C.c_int32), ("pad2_", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

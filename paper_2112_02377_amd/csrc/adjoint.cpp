@@ -53,6 +53,7 @@ static void build_transpose(Handle& h)
     PlanParams prm;
     prm.tile_rows = h.opt.tile_rows;
     prm.staged = false;
+    prm.tables = false;                  // the reverse step reads explicit columns
     h.tplan = make_plan(at, {0, n}, prm);
     // A's plan was built on the same permuted matrix: its slot of entry q
     std::vector<int32_t> mapT((size_t)h.tplan.slots, -1);
@@ -70,20 +71,37 @@ static void build_transpose(Handle& h)
     up(h.td.t_map, mapT.data(), mapT.size() * 4);
     h.td.val.alloc((size_t)t.slots * sizeof(double));
     // The gradient pass reads x at global columns of A's slots: a staged plan
-    // stores tile-local offsets, so rebuild the global column of every slot
-    // from the tile's footprint runs.
+    // stores tile-local offsets and a slice with a shift table stores none, so
+    // rebuild the global column of every slot (for a table slice the clamped
+    // column the sweep uses; for staged tiles through the footprint runs).
     const Plan& pl = h.plan;
-    if (pl.colfmt == COL_LOCAL16) {
+    const bool table = pl.colfmt == COL_TABG || pl.colfmt == COL_TABL;
+    if (pl.colfmt == COL_LOCAL16 || table) {
         std::vector<int32_t> gcol((size_t)pl.slots, 0);
         for (int32_t tt = 0; tt < pl.ntiles; ++tt) {
-            const int32_t ra = pl.tile_run0[tt], rb = pl.tile_run0[tt + 1];
-            for (int32_t sl = pl.tile_slice0[tt]; sl < pl.tile_slice0[tt + 1]; ++sl)
-                for (int64_t q = pl.slice_off[sl]; q < pl.slice_off[sl + 1]; ++q) {
-                    const int32_t loc = pl.col16[q];
-                    int32_t r = ra;                       // last run starting at or before loc
-                    while (r + 1 < rb && pl.run_lds[r + 1] <= loc) ++r;
-                    gcol[q] = pl.run_start[r] + (loc - pl.run_lds[r]);
-                }
+            const int32_t ra = pl.prm.staged ? pl.tile_run0[tt] : 0;
+            const int32_t rb = pl.prm.staged ? pl.tile_run0[tt + 1] : 0;
+            const int32_t lim = pl.prm.staged ? pl.tile_fp[tt] : n;
+            auto global = [&](int32_t loc) {
+                int32_t r = ra;                           // last run starting at or before loc
+                while (r + 1 < rb && pl.run_lds[r + 1] <= loc) ++r;
+                return pl.run_start[r] + (loc - pl.run_lds[r]);
+            };
+            for (int32_t sl = pl.tile_slice0[tt]; sl < pl.tile_slice0[tt + 1]; ++sl) {
+                const int64_t tab = pl.slice_off[sl] / kSlice;
+                const int32_t w = pl.slice_width[sl];
+                for (int32_t k = 0; k < w; ++k)
+                    for (int32_t lane = 0; lane < kSlice; ++lane) {
+                        const int64_t q = pl.slice_off[sl] + (int64_t)k * kSlice + lane;
+                        const int32_t i = pl.slice_row0[sl] + lane;
+                        int32_t c;
+                        if (table) c = std::min(std::max(i + pl.shift[(size_t)tab + k], 0), lim - 1);
+                        else if (pl.colfmt == COL_LOCAL16) c = pl.col16[q];
+                        else if (pl.colfmt == COL_REL16) c = i + (int16_t)pl.col16[q];
+                        else c = pl.col32[q];
+                        gcol[q] = pl.prm.staged ? global(c) : c;
+                    }
+            }
         }
         up(h.td.a_gcol, gcol.data(), gcol.size() * 4);
     } else {
@@ -265,7 +283,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         sA.keep = sT.keep;
         desc[1] = sA;
         int gfmt = h.plan.colfmt;
-        if (gfmt == COL_LOCAL16) {
+        if (h.td.a_gcol.p) {
             desc[1].col32 = static_cast<const int32_t*>(h.td.a_gcol.p);
             gfmt = COL_GLOBAL32;
         }

@@ -90,6 +90,7 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     prm.tile_rows = opt.tile_rows;
     prm.lds_elems = opt.lds_elems;
     prm.staged = (mode != JAC_BANDROW);
+    prm.tables = opt.tables != 0;
     Plan pl = make_plan(pa, np.cuts, prm);
     // caller entry -> slot
     std::vector<int32_t> slot_of_caller(a.ci.size());
@@ -128,6 +129,7 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
         d.col16.reset();
         d.tile_run0.reset(); d.run_start.reset(); d.run_lds.reset(); d.tile_fp.reset(); d.tile_own.reset();
     }
+    upload(d.shift, plan.shift, stream);
     upload(d.slot_of_caller, slot_of_caller, stream);
     upload(d.diag_slot, diag32, stream);
     upload(d.perm, part.perm, stream);
@@ -201,10 +203,10 @@ void Handle::get_x_dev(double* out)
                        stream);
 }
 
-int64_t sweep_stream_bytes(int64_t slots, int colfmt, int32_t n, int nrhs, bool fp32)
+int64_t sweep_stream_bytes(int64_t slots, int64_t table_slots, int colfmt, int32_t n, int nrhs, bool fp32)
 {
     const int64_t t = fp32 ? 4 : 8;
-    return slots * (t + (colfmt == COL_GLOBAL32 ? 4 : 2)) + 3 * t * (int64_t)n * nrhs;
+    return slots * t + (slots - table_slots) * (colfmt == COL_GLOBAL32 ? 4 : 2) + 3 * t * (int64_t)n * nrhs;
 }
 
 // Auto: a launch whose sweep streams at most the Infinity Cache's 256 MiB
@@ -221,7 +223,7 @@ int32_t keep_matrix(int32_t policy, int64_t bytes)
 
 int64_t Handle::stream_bytes(bool fp32) const
 {
-    return sweep_stream_bytes(plan.slots, plan.colfmt, a.n, nrhs, fp32);
+    return sweep_stream_bytes(plan.slots, plan.table_slots, plan.colfmt, a.n, nrhs, fp32);
 }
 
 SysDev Handle::sysdev(bool fp32) const
@@ -239,6 +241,7 @@ SysDev Handle::sysdev(bool fp32) const
     s.run_lds = static_cast<const int32_t*>(d.run_lds.p);
     s.tile_fp = static_cast<const int32_t*>(d.tile_fp.p);
     s.tile_own = static_cast<const int32_t*>(d.tile_own.p);
+    s.shift = static_cast<const int32_t*>(d.shift.p);
     if (fp32) {
         s.val = d.val32.p;
         s.invd = d.invd32.p;
@@ -840,6 +843,9 @@ jac_status jac_set_option(jac_handle h, jac_option opt, int64_t v)
         case JAC_OPT_CACHE:
             if (v < 0 || v > 2) fail(JAC_E_INVALID, "cache policy: 0, 1 or 2");
             o.cache = (int32_t)v; break;
+        case JAC_OPT_SHIFT_TABLES:
+            if (v != 0 && v != 1) fail(JAC_E_INVALID, "shift tables: 0 or 1");
+            o.tables = (int32_t)v; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -863,6 +869,7 @@ jac_status jac_get_option(jac_handle h, jac_option opt, int64_t* v)
         case JAC_OPT_TIMING: *v = o.timing; break;
         case JAC_OPT_PARTITIONER: *v = o.partitioner; break;
         case JAC_OPT_CACHE: *v = o.cache; break;
+        case JAC_OPT_SHIFT_TABLES: *v = o.tables; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -884,12 +891,14 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.ntiles = h->plan.ntiles;
         i.nslices = h->plan.nslices;
         i.max_footprint = h->plan.max_fp;
-        i.col_bytes = h->plan.colfmt == COL_GLOBAL32 ? 4 : 2;
+        const int cf = h->plan.colfmt;
+        i.col_bytes = cf == COL_GLOBAL32 ? 4 : (cf == COL_REL16 || cf == COL_LOCAL16) ? 2 : 0;
+        i.col_format = cf;
         i.halo_entries = (int64_t)h->part.recv_idx.size();
         i.staged_entries = h->plan.staged_entries;
         i.alg_bytes_per_sweep = 12 * nnz + 4 * (n + 1) + 8 * n + 24 * n * r;
-        int64_t dev = h->plan.slots * (8 + i.col_bytes) + 24 * n * r;
-        dev += (int64_t)h->plan.nslices * (4 + 4 + 8);
+        int64_t dev = h->plan.slots * 8 + (h->plan.slots - h->plan.table_slots) * i.col_bytes + 24 * n * r;
+        dev += (int64_t)h->plan.nslices * (4 + 4 + 8) + (int64_t)(h->plan.table_slots / kSlice) * 4;
         if (h->plan.prm.staged) dev += (h->plan.staged_entries - n) * 8 * r + (int64_t)h->plan.run_start.size() * 8;
         i.dev_bytes_per_sweep = dev;
         i.loop_grid = h->last_grid;
@@ -898,6 +907,7 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.last_loop_sweeps = h->last_loop_sweeps;
         i.keep_matrix = keep_matrix(h->opt.cache, h->stream_bytes(false));
         i.state_gen = h->state_gen;
+        i.table_slots = h->plan.table_slots;
         *info = i;
         return JAC_OK;
     });

@@ -40,12 +40,13 @@ struct Options {
     int32_t timing = 0;
     int32_t partitioner = 0;
     int32_t cache = 0;         // matrix loads: 0 auto, 1 keep in cache, 2 stream (nontemporal)
+    int32_t tables = 1;        // per-slice column shift tables where they stream fewer bytes
 };
 
 // Bytes one sweep streams from memory when the matrix is loaded from the
-// caches no more than once: values and column entries of every stored slot,
-// and b, x_k and x_{k+1}.
-int64_t sweep_stream_bytes(int64_t slots, int colfmt, int32_t n, int nrhs, bool fp32);
+// caches no more than once: values of every stored slot, column entries of
+// the slots outside shift-table slices, and b, x_k and x_{k+1}.
+int64_t sweep_stream_bytes(int64_t slots, int64_t table_slots, int colfmt, int32_t n, int nrhs, bool fp32);
 // The temporal/nontemporal choice for matrix loads of a launch that streams
 // `bytes` per sweep under cache policy `policy`.
 int32_t keep_matrix(int32_t policy, int64_t bytes);
@@ -53,6 +54,7 @@ int32_t keep_matrix(int32_t policy, int64_t bytes);
 struct DeviceArrays {
     DevMem tile_row0, tile_slice0, slice_row0, slice_width, slice_off;
     DevMem col32, col16, tile_run0, run_start, run_lds, tile_fp, tile_own;
+    DevMem shift;                          // shift-table formats: shifts per slot column
     DevMem slot_of_caller, diag_slot, perm;
     DevMem vals_caller, b_caller;          // caller order, kept for re-planning
     DevMem val, val32, invd, invd32;

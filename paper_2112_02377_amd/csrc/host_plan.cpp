@@ -9,6 +9,13 @@
 // The footprint is the single-device form of the paper's dependency lists
 // (section 4.2.2) and interface exchange (section 4.3): a tile reads from
 // memory exactly the x values its rows need, once, into LDS.
+//
+// A slice whose rows reach their columns through few distinct shifts (column
+// minus row, or for staged tiles LDS position minus row: a stencil has one
+// per neighbour) stores no column per slot at all: slot k holds every row's
+// entry of the slice's k-th shift, and the kernel forms the column from the
+// row.  The planner takes that layout for a slice when it streams fewer
+// bytes (8 per slot against 8 + 2 or 8 + 4 with explicit columns).
 #include <algorithm>
 #include <numeric>
 
@@ -78,30 +85,7 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
     pl.ntiles = (int32_t)pl.tile_row0.size() - 1;
     if (!staged) { prm.staged = false; fps.clear(); }
 
-    // 2. slices and slot layout
-    pl.tile_slice0.assign((size_t)pl.ntiles + 1, 0);
-    pl.slice_row0.clear();
-    pl.slice_width.clear();
-    pl.slice_off.assign(1, 0);
-    for (int32_t t = 0; t < pl.ntiles; ++t) {
-        pl.tile_slice0[t] = (int32_t)pl.slice_row0.size();
-        for (int32_t r = pl.tile_row0[t]; r < pl.tile_row0[t + 1]; r += kSlice) {
-            const int32_t re = std::min(pl.tile_row0[t + 1], r + kSlice);
-            int32_t w = 0;
-            for (int32_t i = r; i < re; ++i) w = std::max(w, a.rp[i + 1] - a.rp[i]);
-            pl.slice_row0.push_back(r);
-            pl.slice_width.push_back(w);
-            pl.slice_off.push_back(pl.slice_off.back() + (int64_t)w * kSlice);
-        }
-    }
-    pl.tile_slice0[pl.ntiles] = (int32_t)pl.slice_row0.size();
-    pl.nslices = (int32_t)pl.slice_row0.size();
-    pl.slots = pl.slice_off.back();
-    if (pl.slots >= ((int64_t)1 << 31)) fail(JAC_E_INVALID, "matrix too large for 32-bit slot indices");
-
-    // 3. columns per slot, entry -> slot map, diagonal slots
-    pl.slot_of_nnz.assign(a.ci.size(), -1);
-    pl.diag_slot.assign((size_t)n, -1);
+    // 2. explicit column format, then slices and slot layout
     bool rel16 = false;
     if (!prm.staged && prm.rel16) {
         int64_t maxd = 0;
@@ -110,15 +94,71 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         rel16 = maxd <= 32767;            // dead lanes point back to their slice's first row
     }
     pl.colfmt = prm.staged ? COL_LOCAL16 : (rel16 ? COL_REL16 : COL_GLOBAL32);
-    if (rel16) pl.col16.assign((size_t)pl.slots, 0);
+    const int64_t col_bytes = pl.colfmt == COL_GLOBAL32 ? 4 : 2;
+    // the shift of entry (i, c): c - i, or its LDS position in tile t minus i
+    auto shift_of = [&](int32_t t, int32_t i, int32_t c) -> int32_t {
+        if (!prm.staged) return c - i;
+        const std::vector<int32_t>& cols = fps[t].cols;
+        return (int32_t)(std::lower_bound(cols.begin(), cols.end(), c) - cols.begin()) - i;
+    };
+    pl.tile_slice0.assign((size_t)pl.ntiles + 1, 0);
+    pl.slice_row0.clear();
+    pl.slice_width.clear();
+    pl.slice_off.assign(1, 0);
+    pl.shift.clear();
+    std::vector<int32_t> w_ell, w_tab;          // per slice
+    std::vector<int32_t> keys;
+    int64_t ell_bytes = 0, tab_bytes = 0;
+    for (int32_t t = 0; t < pl.ntiles; ++t) {
+        pl.tile_slice0[t] = (int32_t)pl.slice_row0.size();
+        for (int32_t r = pl.tile_row0[t]; r < pl.tile_row0[t + 1]; r += kSlice) {
+            const int32_t re = std::min(pl.tile_row0[t + 1], r + kSlice);
+            int32_t w = 0;
+            for (int32_t i = r; i < re; ++i) w = std::max(w, a.rp[i + 1] - a.rp[i]);
+            int32_t wt = 0;
+            if (prm.tables) {
+                keys.clear();
+                for (int32_t i = r; i < re; ++i)
+                    for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) keys.push_back(shift_of(t, i, a.ci[p]));
+                std::sort(keys.begin(), keys.end());
+                keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+                wt = (int32_t)keys.size();
+                pl.shift.insert(pl.shift.end(), keys.begin(), keys.end());
+            }
+            pl.slice_row0.push_back(r);
+            w_ell.push_back(w);
+            w_tab.push_back(wt);
+            ell_bytes += (int64_t)w * kSlice * (8 + col_bytes);
+            tab_bytes += (int64_t)wt * kSlice * 8;
+        }
+    }
+    // one format for the whole plan: the kernels then carry no per-slice choice
+    const bool tables = prm.tables && tab_bytes < ell_bytes;
+    if (tables) pl.colfmt = prm.staged ? COL_TABL : COL_TABG;
+    else pl.shift.clear();
+    for (size_t s = 0; s < w_ell.size(); ++s) {
+        const int32_t w = tables ? w_tab[s] : w_ell[s];
+        pl.slice_width.push_back(w);
+        pl.slice_off.push_back(pl.slice_off.back() + (int64_t)w * kSlice);
+    }
+    pl.table_slots = tables ? pl.slice_off.back() : 0;
+    pl.tile_slice0[pl.ntiles] = (int32_t)pl.slice_row0.size();
+    pl.nslices = (int32_t)pl.slice_row0.size();
+    pl.slots = pl.slice_off.back();
+    if (pl.slots >= ((int64_t)1 << 31)) fail(JAC_E_INVALID, "matrix too large for 32-bit slot indices");
+
+    // 3. columns per slot, entry -> slot map, diagonal slots
+    pl.slot_of_nnz.assign(a.ci.size(), -1);
+    pl.diag_slot.assign((size_t)n, -1);
+    if (rel16 && !tables) pl.col16.assign((size_t)pl.slots, 0);
     if (prm.staged) {
-        pl.col16.assign((size_t)pl.slots, 0);
+        if (!tables) pl.col16.assign((size_t)pl.slots, 0);
         pl.tile_run0.assign((size_t)pl.ntiles + 1, 0);
         pl.tile_fp.assign((size_t)pl.ntiles, 0);
         pl.tile_own.assign((size_t)pl.ntiles, 0);
         pl.run_start.clear();
         pl.run_lds.clear();
-    } else if (!rel16) {
+    } else if (!rel16 && !tables) {
         pl.col32.assign((size_t)pl.slots, 0);
     }
     pl.max_fp = 0;
@@ -147,6 +187,20 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
             const int32_t row0 = pl.slice_row0[s];
             const int32_t w = pl.slice_width[s];
             const int64_t off = pl.slice_off[s];
+            if (tables) {
+                // each entry goes to the slot of its shift; the other slots
+                // keep zero values and no columns
+                const int32_t* sh = pl.shift.data() + off / kSlice;
+                for (int32_t i = row0; i < std::min(r1, row0 + kSlice); ++i)
+                    for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+                        const int32_t key = shift_of(t, i, a.ci[p]);
+                        const int32_t k = (int32_t)(std::lower_bound(sh, sh + w, key) - sh);
+                        const int64_t slot = off + (int64_t)k * kSlice + (i - row0);
+                        pl.slot_of_nnz[p] = slot;
+                        if (a.ci[p] == i) pl.diag_slot[i] = slot;
+                    }
+                continue;
+            }
             for (int32_t lane = 0; lane < kSlice; ++lane) {
                 const int32_t i = row0 + lane;
                 const bool live = i < r1;
@@ -183,6 +237,8 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         }
     }
     if (prm.staged) pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+    // a batch of slots may read up to 7 shifts past the last slice's last one
+    if (tables) pl.shift.insert(pl.shift.end(), kSlice, 0);
     return pl;
 }
 

@@ -68,10 +68,14 @@ struct PlanParams {
     int32_t max_runs = 1024;        // max footprint runs per tile
     bool staged = false;            // stage x through LDS with 16-bit local columns
     bool rel16 = true;              // unstaged: 16-bit row-relative columns when every |j - i| fits
+    bool tables = true;             // per-slice tables of column shifts where they stream fewer bytes
 };
 
-// Column index format of the sliced layout.
-enum ColFormat { COL_GLOBAL32 = 0, COL_REL16 = 1, COL_LOCAL16 = 2 };
+// Column index format of the sliced layout: a column per slot (global int32,
+// row-relative int16, tile-local uint16), or none and a table of column
+// shifts per slice (unstaged: column = row + shift; staged: LDS position =
+// row + shift).
+enum ColFormat { COL_GLOBAL32 = 0, COL_REL16 = 1, COL_LOCAL16 = 2, COL_TABG = 3, COL_TABL = 4 };
 
 struct Plan {
     PlanParams prm;
@@ -95,6 +99,12 @@ struct Plan {
     std::vector<int32_t> tile_own;    // LDS offset of the tile's own first row
     int32_t max_fp = 0, max_runs = 0;
     int64_t staged_entries = 0;
+    // shift-table formats (COL_TABG, COL_TABL): slot k of slice s holds, for
+    // row i, the entry of column i + shift[slice_off[s] / 64 + k] (unstaged)
+    // or of LDS position i + shift[...] (staged) if the row has one, else a
+    // zero (the kernel clamps the column into range); 64 trailing zeros
+    std::vector<int32_t> shift;
+    int64_t table_slots = 0;          // slots when the plan uses a shift table
 };
 
 Plan make_plan(const Csr& pa, const std::vector<int32_t>& cuts, const PlanParams& prm);

@@ -24,6 +24,7 @@ struct SysDev {
     const int32_t* run_lds;
     const int32_t* tile_fp;
     const int32_t* tile_own;
+    const int32_t* shift;     // shift-table formats: one shift per slot column (slots / 64)
     const void* val;          // slot values, T
     const void* invd;         // D^{-1}, T
     const void* b;            // right-hand sides, T, node-major [n][nrhs]

@@ -179,7 +179,8 @@ __device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t
             a[u] = ldm<NT>(&val[slot]);
             if constexpr (CM == COL_GLOBAL32) raw[u] = ldm<NT>(&col32[slot]);
             else if constexpr (CM == COL_REL16) raw[u] = (int16_t)ldm<NT>(&col16[slot]);
-            else raw[u] = ldm<NT>(&col16[slot]);
+            else if constexpr (CM == COL_LOCAL16) raw[u] = ldm<NT>(&col16[slot]);
+            else raw[u] = 0;                      // shift-table formats store no columns
         }
 }
 
@@ -201,10 +202,15 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
     const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
     const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
+    const cptr<const int32_t> shift = (cptr<const int32_t>)S.shift;
     const int32_t r0 = tile_row0[tile];
     const int32_t r1 = tile_row0[tile + 1];
     int32_t own = 0;
-    constexpr bool STAGED = CM == COL_LOCAL16;
+    int32_t lim = S.n;                            // columns (or LDS positions) are below lim
+    constexpr bool STAGED = CM == COL_LOCAL16 || CM == COL_TABL;
+    // shift-table formats: slot k of slice s is the entry of column (or LDS
+    // position) i + shift[slice_off[s] / 64 + k] of every row i of the slice
+    constexpr bool TAB = CM == COL_TABG || CM == COL_TABL;
     if constexpr (STAGED) {
         const gptr<const int32_t> run_start = (gptr<const int32_t>)S.run_start;
         const gptr<const int32_t> run_lds = (gptr<const int32_t>)S.run_lds;
@@ -212,6 +218,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         const int32_t nr = ((cptr<const int32_t>)S.tile_run0)[tile + 1] - run0;
         const int32_t fp = ((cptr<const int32_t>)S.tile_fp)[tile];
         own = ((cptr<const int32_t>)S.tile_own)[tile];
+        lim = fp;
         for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) {
             lds_rs[t] = run_start[run0 + t];
             lds_ro[t] = run_lds[run0 + t];
@@ -274,6 +281,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) { q[c] = Vec<T>::zero(); xi[c] = Vec<T>::zero(); }
         const int32_t self = STAGED ? own + (i - r0) : i;   // column index of the diagonal
+        const int64_t sbase = soff >> 6;                    // the slice's first shift
         for (int32_t k0 = 0; k0 < w; k0 += KB) {
             // all value / column loads of the batch first, decoded afterwards,
             // so that none waits for another
@@ -285,7 +293,10 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
 #pragma unroll
             for (int u = 0; u < KB; ++u)
                 if (k0 + u < w) {
-                    col[u] = (CM == COL_REL16) ? i + raw[u] : raw[u];
+                    // a table slot that a row does not use holds a zero: its
+                    // column is only clamped into range
+                    if constexpr (TAB) col[u] = min(max(i + shift[sbase + k0 + u], 0), lim - 1);
+                    else col[u] = (CM == COL_REL16) ? i + raw[u] : raw[u];
 #pragma unroll
                     for (int c = 0; c < NRHS; ++c) {
                         if constexpr (STAGED) xv[u][c] = lds_x[col[u] * NRHS + c];
@@ -510,7 +521,7 @@ __global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
             sweep_tile<double, NRHS, CM, NT, false, true>(S, tile, x, x, 0u, false, lds_x, lds_rs, lds_ro, acc);
-            if constexpr (CM == COL_LOCAL16) __syncthreads();    // the next tile restages the LDS
+            if constexpr (CM == COL_LOCAL16 || CM == COL_TABL) __syncthreads();   // the next tile restages the LDS
         }
 }
 
@@ -850,6 +861,8 @@ void* pick_cm(int colfmt, int loop)
     case COL_GLOBAL32: return kfn<T, NRHS, COL_GLOBAL32, NT>(loop);
     case COL_REL16: return kfn<T, NRHS, COL_REL16, NT>(loop);
     case COL_LOCAL16: return kfn<T, NRHS, COL_LOCAL16, NT>(loop);
+    case COL_TABG: return kfn<T, NRHS, COL_TABG, NT>(loop);
+    case COL_TABL: return kfn<T, NRHS, COL_TABL, NT>(loop);
     default: return nullptr;
     }
 }
@@ -929,6 +942,8 @@ void* async_cm(int colfmt)
     switch (colfmt) {
     case COL_GLOBAL32: return reinterpret_cast<void*>(&k_async<NRHS, COL_GLOBAL32, NT>);
     case COL_REL16: return reinterpret_cast<void*>(&k_async<NRHS, COL_REL16, NT>);
+    case COL_TABG: return reinterpret_cast<void*>(&k_async<NRHS, COL_TABG, NT>);
+    case COL_TABL: return reinterpret_cast<void*>(&k_async<NRHS, COL_TABL, NT>);
     default: return reinterpret_cast<void*>(&k_async<NRHS, COL_LOCAL16, NT>);
     }
 }
@@ -966,6 +981,8 @@ void* resid_fn(int colfmt)
     switch (colfmt) {
     case COL_GLOBAL32: return reinterpret_cast<void*>(&k_resid<NRHS, COL_GLOBAL32>);
     case COL_REL16: return reinterpret_cast<void*>(&k_resid<NRHS, COL_REL16>);
+    case COL_TABG: return reinterpret_cast<void*>(&k_resid<NRHS, COL_TABG>);
+    case COL_TABL: return reinterpret_cast<void*>(&k_resid<NRHS, COL_TABL>);
     default: return reinterpret_cast<void*>(&k_resid<NRHS, COL_LOCAL16>);
     }
 }

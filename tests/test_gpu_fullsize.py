@@ -14,8 +14,9 @@ parts under each split, the bench's default tile shape and loop:
   per sweep, under 40 eps max(1, max|x|) here (|b_i| <= 12, |x| ~ 1), and
   the Jacobi matrix has infinity norm 1, so after K sweeps the bound is
   K * 50 eps max(1, max|x|);
-* the 192^3 control, whose band reaches past 16-bit row offsets (32-bit
-  columns), a few sweeps against the oracle under the same bound;
+* the 192^3 control, whose band reaches past 16-bit row offsets (a shift
+  table, or 32-bit columns without tables), a few sweeps against the oracle
+  under the same bound;
 * the 96^3 27-point FE-like system of the refinement comparison: FP64 and
   FP32-inner solves to 1e-10 against the oracle's FP64 solve;
 * the 256-system, 4-right-hand-side batch of the batched comparison: every
@@ -93,17 +94,23 @@ def test_bench_sweeps_against_the_oracle(big, mode, P, sub):
     b.jac_destroy(h)
 
 
-def test_192_control_uses_32_bit_columns():
+def test_192_control_shift_table_and_32_bit_columns():
+    # the band reaches past 16-bit row offsets: a shift table by default, 32-bit
+    # columns without tables; both bit-identical and against the oracle
     need_gpu()
     b = B()
     s = W.laplace7(192, workload=2)
     K = 6
-    h = make(s, 1, 64)
-    info = b.jac_get_info(h)
-    assert info["col_bytes"] == 4 and info["n"] == 7077888 and info["nnz"] == 49324032
-    hist = sweep(h, K)[:, 0]
-    x = get_x(h, s.n)[0]
-    b.jac_destroy(h)
+    out = []
+    for tab, fmt, cb in ((1, 3, 0), (0, 0, 4)):
+        h = make(s, 1, 64, opts={b.JAC_OPT_SHIFT_TABLES: tab})
+        info = b.jac_get_info(h)
+        assert info["col_format"] == fmt and info["col_bytes"] == cb
+        assert info["n"] == 7077888 and info["nnz"] == 49324032
+        out.append((sweep(h, K)[:, 0], get_x(h, s.n)[0]))
+        b.jac_destroy(h)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    hist, x = out[0]
     _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K, threads=16)
     bound = K * 50 * EPS * max(1.0, np.abs(xr).max())
     assert np.abs(x - xr).max() <= bound

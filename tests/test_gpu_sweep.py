@@ -212,7 +212,8 @@ def test_column_formats_match_oracle():
     narrow = W.laplace7(9, workload=1)
     wide = W.diffusion_system(200, 190, 2, np.full(200 * 190 * 2, 1.0), np.ones(200 * 190 * 2))
     for s, cb in ((narrow, 2), (wide, 4)):
-        h = make(s, 1, 3)
+        # explicit columns (the shift tables would take both)
+        h = make(s, 1, 3, opts={b.JAC_OPT_SHIFT_TABLES: 0})
         assert b.jac_get_info(h)["col_bytes"] == cb
         hist = sweep(h, 40)[:, 0]
         _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], 40)
