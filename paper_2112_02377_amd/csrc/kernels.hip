@@ -185,6 +185,25 @@ __device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t
 }
 
 // NT: matrix loads with the nontemporal hint (the host chooses per launch).
+// The sweep's batch, branch-free: slots past the slice's width re-read its
+// last slot (a cache hit) and the caller zeroes their values, so every load,
+// gather and multiply-add of the batch is issued without a branch around it.
+template <bool NT, typename T, int CM>
+__device__ __forceinline__ void load_batch_clamped(gptr<const T> val, gptr<const int32_t> col32,
+                                                   gptr<const uint16_t> col16, int64_t off, int32_t k0, int32_t w,
+                                                   T (&a)[KB], int32_t (&raw)[KB])
+{
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+        const int64_t slot = off + (int64_t)min(k0 + u, w - 1) * 64;
+        a[u] = ldm<NT>(&val[slot]);
+        if constexpr (CM == COL_GLOBAL32) raw[u] = ldm<NT>(&col32[slot]);
+        else if constexpr (CM == COL_REL16) raw[u] = (int16_t)ldm<NT>(&col16[slot]);
+        else if constexpr (CM == COL_LOCAL16) raw[u] = ldm<NT>(&col16[slot]);
+        else raw[u] = 0;                          // shift-table formats store no columns
+    }
+}
+
 template <typename T, int NRHS, int CM, bool NT, bool RESID = false, bool COH = false>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
                                            bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
@@ -287,34 +306,34 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             // so that none waits for another
             T a[KB];
             int32_t raw[KB];
-            load_batch<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
+            load_batch_clamped<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
             int32_t col[KB];
             T xv[KB][NRHS];
 #pragma unroll
-            for (int u = 0; u < KB; ++u)
-                if (k0 + u < w) {
-                    // a table slot that a row does not use holds a zero: its
-                    // column is only clamped into range
-                    if constexpr (TAB) col[u] = min(max(i + shift[sbase + k0 + u], 0), lim - 1);
-                    else col[u] = (CM == COL_REL16) ? i + raw[u] : raw[u];
+            for (int u = 0; u < KB; ++u) {
+                const int32_t ku = min(k0 + u, w - 1);
+                // a table slot that a row does not use holds a zero: its
+                // column is only clamped into range
+                if constexpr (TAB) col[u] = min(max(i + shift[sbase + ku], 0), lim - 1);
+                else col[u] = (CM == COL_REL16) ? i + raw[u] : raw[u];
 #pragma unroll
-                    for (int c = 0; c < NRHS; ++c) {
-                        if constexpr (STAGED) xv[u][c] = lds_x[col[u] * NRHS + c];
-                        else xv[u][c] = ldx<T, COH>(&x_[(int64_t)col[u] * NRHS + c]);
-                    }
+                for (int c = 0; c < NRHS; ++c) {
+                    if constexpr (STAGED) xv[u][c] = lds_x[col[u] * NRHS + c];
+                    else xv[u][c] = ldx<T, COH>(&x_[(int64_t)col[u] * NRHS + c]);
                 }
+                if (k0 + u >= w) a[u] = (T)0;            // slot past the width: adds nothing
+            }
 #pragma unroll
-            for (int u = 0; u < KB; ++u)
-                if (k0 + u < w) {
+            for (int u = 0; u < KB; ++u) {
 #pragma unroll
-                    for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
-                    // the stored diagonal is nonzero; padding slots hold 0
-                    if (col[u] == self && a[u] != (T)0) {
-                        d = a[u];
+                for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
+                // the stored diagonal is nonzero; padding slots hold 0
+                if (col[u] == self && a[u] != (T)0) {
+                    d = a[u];
 #pragma unroll
-                        for (int c = 0; c < NRHS; ++c) xi[c] = xv[u][c];
-                    }
+                    for (int c = 0; c < NRHS; ++c) xi[c] = xv[u][c];
                 }
+            }
         }
         if (i < r1) {
             // D^{-1}: the correctly rounded reciprocal of the diagonal, the same
