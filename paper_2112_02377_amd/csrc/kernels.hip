@@ -185,9 +185,11 @@ __device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t
 }
 
 // NT: matrix loads with the nontemporal hint (the host chooses per launch).
-// The sweep's batch, branch-free: slots past the slice's width re-read its
-// last slot (a cache hit) and the caller zeroes their values, so every load,
-// gather and multiply-add of the batch is issued without a branch around it.
+// The FP64 sweep's batch, branch-free: slots past the slice's width re-read
+// its last slot (a cache hit) and the caller zeroes their values, so every
+// load, gather and multiply-add of the batch is issued without a branch
+// around it.  (The FP32 sweep keeps the guarded batch: the clamped one costs
+// it a wave per SIMD.)
 template <bool NT, typename T, int CM>
 __device__ __forceinline__ void load_batch_clamped(gptr<const T> val, gptr<const int32_t> col32,
                                                    gptr<const uint16_t> col16, int64_t off, int32_t k0, int32_t w,
@@ -304,13 +306,16 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         for (int32_t k0 = 0; k0 < w; k0 += KB) {
             // all value / column loads of the batch first, decoded afterwards,
             // so that none waits for another
+            constexpr bool BF = sizeof(T) == 8;
             T a[KB];
             int32_t raw[KB];
-            load_batch_clamped<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
+            if constexpr (BF) load_batch_clamped<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
+            else load_batch<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
             int32_t col[KB];
             T xv[KB][NRHS];
 #pragma unroll
             for (int u = 0; u < KB; ++u) {
+                if (!BF && k0 + u >= w) continue;
                 const int32_t ku = min(k0 + u, w - 1);
                 // a table slot that a row does not use holds a zero: its
                 // column is only clamped into range
@@ -325,6 +330,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             }
 #pragma unroll
             for (int u = 0; u < KB; ++u) {
+                if (!BF && k0 + u >= w) continue;
 #pragma unroll
                 for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
                 // the stored diagonal is nonzero; padding slots hold 0
