@@ -11,7 +11,11 @@
 // segment.  Staged tiles first copy the x entries their rows reference into
 // LDS (the single-device form of the paper's dependency-list exchange,
 // section 4.2.2, and interface exchange, section 4.3) and then gather from LDS
-// through 16-bit tile-local column indices.
+// through 16-bit tile-local column indices.  Splits whose slices reach their
+// columns through few distinct shifts (stencil matrices) store no column per
+// slot: the column (or LDS position) is the row plus the slot's shift.
+// Every sweep kernel exists twice, with temporal and with nontemporal matrix
+// loads; the host picks per launch whether the matrix stays in the caches.
 //
 // The norm (section 3 algorithm; section 4.2.3, local sums combined by an
 // all-reduce) is reduced deterministically: fixed shuffle tree in a wave,
@@ -21,6 +25,8 @@
 // sweep).  No floating point atomics are used anywhere, so reruns are
 // bit-identical.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include <cmath>
 #include <cstdint>
@@ -216,29 +222,35 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     const gptr<float> rout = (gptr<float>)rout_;
     // every array below is device memory: global address space for the loads
     const gptr<T> xn = (gptr<T>)xn_;
-    const gptr<const T> val = (gptr<const T>)S.val;
-    const gptr<const T> b = (gptr<const T>)S.b;
-    const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
-    const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
-    const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
-    const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
-    const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
-    const cptr<const int32_t> shift = (cptr<const int32_t>)S.shift;
+    // the descriptor (in device memory no kernel writes) is read through the
+    // constant address space, so its fields land in scalar registers instead
+    // of vector ones (FP64 only: the FP32 sweep has vector registers to spare
+    // and would lose a wave per SIMD to the scalar ones)
+    using DescPtr = std::conditional_t<sizeof(T) == 8, cptr<const SysDev>, const SysDev*>;
+    const DescPtr D = (DescPtr)&S;
+    const gptr<const T> val = (gptr<const T>)D->val;
+    const gptr<const T> b = (gptr<const T>)D->b;
+    const gptr<const int32_t> col32 = (gptr<const int32_t>)D->col32;
+    const gptr<const uint16_t> col16 = (gptr<const uint16_t>)D->col16;
+    const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)D->tile_row0;
+    const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)D->tile_slice0;
+    const cptr<const int64_t> slice_off = (cptr<const int64_t>)D->slice_off;
+    const cptr<const int32_t> shift = (cptr<const int32_t>)D->shift;
     const int32_t r0 = tile_row0[tile];
     const int32_t r1 = tile_row0[tile + 1];
     int32_t own = 0;
-    int32_t lim = S.n;                            // columns (or LDS positions) are below lim
+    int32_t lim = D->n;                            // columns (or LDS positions) are below lim
     constexpr bool STAGED = CM == COL_LOCAL16 || CM == COL_TABL;
     // shift-table formats: slot k of slice s is the entry of column (or LDS
     // position) i + shift[slice_off[s] / 64 + k] of every row i of the slice
     constexpr bool TAB = CM == COL_TABG || CM == COL_TABL;
     if constexpr (STAGED) {
-        const gptr<const int32_t> run_start = (gptr<const int32_t>)S.run_start;
-        const gptr<const int32_t> run_lds = (gptr<const int32_t>)S.run_lds;
-        const int32_t run0 = ((cptr<const int32_t>)S.tile_run0)[tile];
-        const int32_t nr = ((cptr<const int32_t>)S.tile_run0)[tile + 1] - run0;
-        const int32_t fp = ((cptr<const int32_t>)S.tile_fp)[tile];
-        own = ((cptr<const int32_t>)S.tile_own)[tile];
+        const gptr<const int32_t> run_start = (gptr<const int32_t>)D->run_start;
+        const gptr<const int32_t> run_lds = (gptr<const int32_t>)D->run_lds;
+        const int32_t run0 = ((cptr<const int32_t>)D->tile_run0)[tile];
+        const int32_t nr = ((cptr<const int32_t>)D->tile_run0)[tile + 1] - run0;
+        const int32_t fp = ((cptr<const int32_t>)D->tile_fp)[tile];
+        own = ((cptr<const int32_t>)D->tile_own)[tile];
         lim = fp;
         for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) {
             lds_rs[t] = run_start[run0 + t];
@@ -418,8 +430,14 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
 // One launch per sweep (single system).  Workgroups 0..ntiles-1 sweep one tile
 // each; the last workgroup takes the stop decision on the previous sweep.
 // ---------------------------------------------------------------------------
+// The FP64 single right-hand-side sweep on the shift-table formats fits 8
+// waves per SIMD once some scalar registers spill to vector lanes (outside
+// the slot loop); it measured faster that way than with 7 waves and no
+// spills.
 template <typename T, int NRHS, int CM, bool NT>
-__global__ void __launch_bounds__(512) k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(NRHS == 1 && sizeof(T) == 8 && (CM == COL_TABG || CM == COL_TABL) ? 8 : 1)))
+k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
 {
     extern __shared__ __align__(16) char smem[];
     const SysDev& S = P.sys[0];
