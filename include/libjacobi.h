@@ -106,7 +106,7 @@ typedef enum {
                                 solve decides on the bytes of the systems still
                                 running (per-sweep launches: again whenever a
                                 system stops; persistent launch: once)         */
-    JAC_OPT_SHIFT_TABLES = 12 /* 1 (default): when the slices of a split reach
+    JAC_OPT_SHIFT_TABLES = 12,/* 1 (default): when the slices of a split reach
                                 their columns through few distinct shifts
                                 (column minus row, or LDS position minus row
                                 for staged tiles; one per stencil neighbour),
@@ -114,6 +114,15 @@ typedef enum {
                                 column per slot, if that streams fewer bytes
                                 over the whole split; 0: never.  Results are
                                 bit-identical either way                       */
+    JAC_OPT_GRID = 13         /* workgroups of the one-launch-per-sweep loop of a
+                                single system: 1 = one per tile; 2 = one
+                                resident round (as many as the device holds at
+                                once), each sweeping consecutive tiles; 0 =
+                                auto (default): 2 when every tile of the split
+                                costs about the same (largest within 1.25x of
+                                the mean, counting streamed bytes and footprint
+                                runs), else 1.  Results are bit-identical
+                                either way (jac_info.loop_grid reports it)     */
 } jac_option;
 
 typedef struct {

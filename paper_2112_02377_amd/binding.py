@@ -25,7 +25,7 @@ JAC_NORM_L2_REL, JAC_NORM_INF_ABS = 0, 1
 JAC_FP64, JAC_FP32_REFINE = 0, 1
 (JAC_OPT_TILE_ROWS, JAC_OPT_BLOCK, JAC_OPT_LDS_ELEMS, JAC_OPT_LOOP, JAC_OPT_WG_PER_CU, JAC_OPT_INNER_TOL,
  JAC_OPT_INNER_MAX, JAC_OPT_CKPT_MEM_MB, JAC_OPT_TIMING, JAC_OPT_PARTITIONER, JAC_OPT_CACHE,
- JAC_OPT_SHIFT_TABLES) = range(1, 13)
+ JAC_OPT_SHIFT_TABLES, JAC_OPT_GRID) = range(1, 14)
 CACHE_AUTO, CACHE_KEEP, CACHE_STREAM = 0, 1, 2
 PART_ROWS, PART_NNZ, PART_GRAPH = 0, 1, 2
 

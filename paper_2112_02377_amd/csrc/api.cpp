@@ -286,6 +286,12 @@ static int num_cus()
     return cus;
 }
 
+// Tile cost spread (largest over mean) up to which per-sweep launches run one
+// resident round of workgroups (JAC_OPT_GRID auto): the band-row splits of
+// the 128^3 Laplacian are at 1.01, substructuring's at 2.8 (8^3 subdomains)
+// and 3.3 (4^3): its interface tiles gather hundreds of footprint runs.
+constexpr double kUniformTiles = 1.25;
+
 int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 {
     int nb = 0;
@@ -422,7 +428,17 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     } else {
         void* fn = sweep_kernel(fp32, nrhs, colfmt, 0, keep);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
-        const int grid = (int)std::max<int64_t>(1, work) + 1;      // + the deciding workgroup
+        // A workgroup per tile lets the dispatcher balance tiles of unequal
+        // cost; when every tile costs about the same, one resident round of
+        // workgroups, each sweeping consecutive tiles of its XCD's share,
+        // saves dispatching and retiring the rest.
+        int64_t wk = std::max<int64_t>(1, work);
+        if (h.opt.grid == 2 || (h.opt.grid == 0 && h.plan.tile_cost_spread <= kUniformTiles)) {
+            int nb = 0;
+            JAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds));
+            wk = std::min<int64_t>(wk, (int64_t)std::max(nb, 1) * num_cus());
+        }
+        const int grid = (int)wk + 1;      // + the deciding workgroup
         h.last_grid = grid;
         if (!solve) {
             for (int32_t k = 0; k < kend; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);
@@ -846,6 +862,9 @@ jac_status jac_set_option(jac_handle h, jac_option opt, int64_t v)
         case JAC_OPT_SHIFT_TABLES:
             if (v != 0 && v != 1) fail(JAC_E_INVALID, "shift tables: 0 or 1");
             o.tables = (int32_t)v; break;
+        case JAC_OPT_GRID:
+            if (v < 0 || v > 2) fail(JAC_E_INVALID, "grid: 0, 1 or 2");
+            o.grid = (int32_t)v; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;
@@ -870,6 +889,7 @@ jac_status jac_get_option(jac_handle h, jac_option opt, int64_t* v)
         case JAC_OPT_PARTITIONER: *v = o.partitioner; break;
         case JAC_OPT_CACHE: *v = o.cache; break;
         case JAC_OPT_SHIFT_TABLES: *v = o.tables; break;
+        case JAC_OPT_GRID: *v = o.grid; break;
         default: fail(JAC_E_INVALID, "unknown option");
         }
         return JAC_OK;

@@ -41,6 +41,7 @@ struct Options {
     int32_t partitioner = 0;
     int32_t cache = 0;         // matrix loads: 0 auto, 1 keep in cache, 2 stream (nontemporal)
     int32_t tables = 1;        // per-slice column shift tables where they stream fewer bytes
+    int32_t grid = 0;          // per-sweep launches: 0 auto, 1 a workgroup per tile, 2 one resident round
 };
 
 // Bytes one sweep streams from memory when the matrix is loaded from the

@@ -237,6 +237,16 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         }
     }
     if (prm.staged) pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+    {
+        double sum = 0.0, mx = 0.0;
+        for (int32_t t = 0; t < pl.ntiles; ++t) {
+            double c = 10.0 * (double)(pl.slice_off[pl.tile_slice0[t + 1]] - pl.slice_off[pl.tile_slice0[t]]);
+            if (prm.staged) c += 8.0 * pl.tile_fp[t] + 256.0 * (pl.tile_run0[t + 1] - pl.tile_run0[t]);
+            sum += c;
+            mx = std::max(mx, c);
+        }
+        pl.tile_cost_spread = sum > 0.0 ? mx / (sum / pl.ntiles) : 1.0;
+    }
     // a batch of slots may read up to 7 shifts past the last slice's last one
     if (tables) pl.shift.insert(pl.shift.end(), kSlice, 0);
     return pl;

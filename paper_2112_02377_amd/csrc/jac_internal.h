@@ -99,6 +99,10 @@ struct Plan {
     std::vector<int32_t> tile_own;    // LDS offset of the tile's own first row
     int32_t max_fp = 0, max_runs = 0;
     int64_t staged_entries = 0;
+    // largest tile cost over the mean, a tile's cost taken as the bytes it
+    // streams (10 per slot, 8 per staged entry) plus 256 per footprint run
+    // (each run is a separate gather of cache lines)
+    double tile_cost_spread = 1.0;
     // shift-table formats (COL_TABG, COL_TABL): slot k of slice s holds, for
     // row i, the entry of column i + shift[slice_off[s] / 64 + k] (unstaged)
     // or of LDS position i + shift[...] (staged) if the row has one, else a
