@@ -115,9 +115,12 @@ typedef enum {
                                 over the whole split; 0: never.  Results are
                                 bit-identical either way                       */
     JAC_OPT_GRID = 13         /* workgroups of the one-launch-per-sweep loop of a
-                                single system: 1 = one per tile; 2 = one
-                                resident round (as many as the device holds at
-                                once), each sweeping consecutive tiles; 0 =
+                                single system (each of the eight XCDs sweeps a
+                                contiguous share of the tiles of about equal
+                                streamed bytes): 1 = one per tile of the
+                                largest share on every XCD; 2 = one resident
+                                round (as many as the device holds at once),
+                                each sweeping consecutive tiles; 0 =
                                 auto (default): 2 when every tile of the split
                                 costs about the same (largest within 1.25x of
                                 the mean, counting streamed bytes and footprint

@@ -171,7 +171,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
         void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);
-        const int grid = std::max(h.plan.ntiles, 1) + 1;
+        const int grid = sweep_grid(h, fn, h.opt.block, lds);
         launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, CK(0), st);
         launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
         for (int32_t k = 0; k < K; ++k) {
@@ -201,7 +201,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
     void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
     const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
     const size_t lds = loop_lds_bytes(fpb, runs, 0);
-    const int grid = std::max(h.plan.ntiles, 1) + 1;
+    const int grid = sweep_grid(h, fn, h.opt.block, lds);
     launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, xb[0], st);
     launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
     LoopParams p{};
@@ -331,7 +331,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
         const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
         const size_t lds = loop_lds_bytes(fpb, runs, 0);
-        const int grid = std::max(h.plan.ntiles, 1) + 1;
+        const int grid = sweep_grid(h, fn, h.opt.block, lds);
         if (K > 0) {
             // lambda_K (internal order), mu_K = D^{-1} lambda_K, gb = mu_K
             double* lin = static_cast<double*>(d.adj_lam0.p);

@@ -261,6 +261,7 @@ SysDev Handle::sysdev(bool fp32) const
     s.colfmt = plan.colfmt;
     s.keep = keep_matrix(opt.cache, stream_bytes(fp32));
     for (int c = 0; c < 4; ++c) { s.thr[c] = 0.0; s.big[c] = 1e300; }
+    for (int x = 0; x < 9; ++x) s.xcd0[x] = plan.xcd_tile0[x];
     return s;
 }
 
@@ -286,11 +287,24 @@ static int num_cus()
     return cus;
 }
 
-// Tile cost spread (largest over mean) up to which per-sweep launches run one
-// resident round of workgroups (JAC_OPT_GRID auto): the band-row splits of
-// the 128^3 Laplacian are at 1.01, substructuring's at 2.8 (8^3 subdomains)
-// and 3.3 (4^3): its interface tiles gather hundreds of footprint runs.
-constexpr double kUniformTiles = 1.25;
+// Workgroups of a one-launch-per-sweep k_sweep of the handle's system, the
+// deciding one included.  A workgroup per tile lets the dispatcher balance
+// tiles of unequal cost (every XCD gets as many workgroups as its share has
+// tiles); when every tile costs about the same, one resident round of
+// workgroups, each sweeping consecutive tiles of its XCD's share, saves
+// dispatching and retiring the rest.
+int sweep_grid(const Handle& h, void* fn, int block, size_t lds)
+{
+    const Plan& pl = h.plan;
+    if (h.opt.grid == 2 || (h.opt.grid == 0 && pl.tile_cost_spread <= kUniformTiles)) {
+        int nb = 0;
+        JAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds));
+        return (int)std::min<int64_t>(std::max(pl.ntiles, 1), (int64_t)std::max(nb, 1) * num_cus()) + 1;
+    }
+    int32_t most = 0;
+    for (int x = 0; x < 8; ++x) most = std::max(most, pl.xcd_tile0[x + 1] - pl.xcd_tile0[x]);
+    return std::max(pl.ntiles, 8 * most) + 1;
+}
 
 int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 {
@@ -428,17 +442,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     } else {
         void* fn = sweep_kernel(fp32, nrhs, colfmt, 0, keep);
         const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
-        // A workgroup per tile lets the dispatcher balance tiles of unequal
-        // cost; when every tile costs about the same, one resident round of
-        // workgroups, each sweeping consecutive tiles of its XCD's share,
-        // saves dispatching and retiring the rest.
-        int64_t wk = std::max<int64_t>(1, work);
-        if (h.opt.grid == 2 || (h.opt.grid == 0 && h.plan.tile_cost_spread <= kUniformTiles)) {
-            int nb = 0;
-            JAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds));
-            wk = std::min<int64_t>(wk, (int64_t)std::max(nb, 1) * num_cus());
-        }
-        const int grid = (int)wk + 1;      // + the deciding workgroup
+        const int grid = sweep_grid(h, fn, block, lds);
         h.last_grid = grid;
         if (!solve) {
             for (int32_t k = 0; k < kend; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);

@@ -130,6 +130,7 @@ struct Handle {
 };
 
 int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work);
+int sweep_grid(const Handle& h, void* fn, int block, size_t lds);
 void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
               DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
               int fp_bytes, int runs, int colfmt, int nrhs, const std::vector<int64_t>* sys_bytes = nullptr);

@@ -247,6 +247,26 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         }
         pl.tile_cost_spread = sum > 0.0 ? mx / (sum / pl.ntiles) : 1.0;
     }
+    {
+        std::vector<double> pre((size_t)pl.ntiles + 1, 0.0);
+        for (int32_t t = 0; t < pl.ntiles; ++t) {
+            double c = 10.0 * (double)(pl.slice_off[pl.tile_slice0[t + 1]] - pl.slice_off[pl.tile_slice0[t]]);
+            if (prm.staged) c += 8.0 * pl.tile_fp[t];
+            pre[t + 1] = pre[t] + c;
+        }
+        int32_t t = 0;
+        const int32_t q = pl.ntiles / 8, r = pl.ntiles % 8;
+        for (int x = 1; x < 8; ++x) {
+            if (pl.tile_cost_spread <= kUniformTiles) {
+                t = x * q + std::min(x, r);
+            } else {
+                while (t < pl.ntiles && pre[t] < pre[pl.ntiles] * x / 8.0) ++t;
+            }
+            pl.xcd_tile0[x] = t;
+        }
+        pl.xcd_tile0[0] = 0;
+        pl.xcd_tile0[8] = pl.ntiles;
+    }
     // a batch of slots may read up to 7 shifts past the last slice's last one
     if (tables) pl.shift.insert(pl.shift.end(), kSlice, 0);
     return pl;

@@ -103,6 +103,13 @@ struct Plan {
     // streams (10 per slot, 8 per staged entry) plus 256 per footprint run
     // (each run is a separate gather of cache lines)
     double tile_cost_spread = 1.0;
+    // tiles of the eight XCDs (workgroup w of a sweep launch runs on XCD
+    // w mod 8): XCD x sweeps tiles xcd_tile0[x] .. xcd_tile0[x+1]-1, equal
+    // counts when the tiles cost alike (spread at most kUniformTiles, where
+    // a resident round of workgroups takes the same number of tiles each),
+    // else contiguous ranges of about equal streamed bytes (10 per slot, 8
+    // per staged entry)
+    int32_t xcd_tile0[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // shift-table formats (COL_TABG, COL_TABL): slot k of slice s holds, for
     // row i, the entry of column i + shift[slice_off[s] / 64 + k] (unstaged)
     // or of LDS position i + shift[...] (staged) if the row has one, else a
@@ -112,5 +119,13 @@ struct Plan {
 };
 
 Plan make_plan(const Csr& pa, const std::vector<int32_t>& cuts, const PlanParams& prm);
+
+// Tile cost spread (largest over mean) up to which a split's tiles count as
+// alike: its per-sweep launches then run one resident round of workgroups
+// (JAC_OPT_GRID auto) over equal tile counts per XCD.  The band-row splits
+// of the 128^3 Laplacian are at 1.01, substructuring's at 2.8 (8^3
+// subdomains) and 3.3 (4^3): its interface tiles gather hundreds of
+// footprint runs.
+constexpr double kUniformTiles = 1.25;
 
 }  // namespace jac

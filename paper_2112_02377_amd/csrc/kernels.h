@@ -36,6 +36,7 @@ struct SysDev {
                               // instantiation that matches
     double thr[4];            // stop thresholds per right-hand side
     double big[4];            // divergence thresholds per right-hand side
+    int32_t xcd0[9];          // single-system sweep launch: XCD x sweeps tiles xcd0[x] .. xcd0[x+1]-1
 };
 
 // Per-system control state.  Every "sweep" field holds kRunning until set,

@@ -455,8 +455,24 @@ k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
 #pragma unroll
     for (int c = 0; c < NRHS; ++c)
         if (st->stop_k[c] < k) frozen |= 1u << c;
+    // XCD x (workgroups w with w mod 8 = x) sweeps its contiguous share of
+    // the tiles, of about equal streamed bytes; a grid of fewer than 8
+    // sweepers strides over all tiles
     int32_t first, end, stride;
-    xcd_items(S.ntiles, gridDim.x - 1, blockIdx.x, first, end, stride);
+    {
+        const int32_t G = gridDim.x - 1, wg = blockIdx.x;
+        if (G < 8) {
+            first = wg;
+            end = S.ntiles;
+            stride = G;
+        } else {
+            const int32_t xx = wg & 7;
+            const cptr<const SysDev> D = (cptr<const SysDev>)&S;
+            first = D->xcd0[xx] + (wg >> 3);
+            end = D->xcd0[xx + 1];
+            stride = (G - xx + 7) >> 3;
+        }
+    }
     const bool is_max = P.norm_inf != 0;
     const T* x = reinterpret_cast<const T*>(S.x[k % 3]);
     T* xn = reinterpret_cast<T*>(S.x[(k + 1) % 3]);

@@ -1,9 +1,10 @@
 """GPU: workgroups of the per-sweep launch (JAC_OPT_GRID).
 
 One workgroup per tile, or one resident round of workgroups each sweeping
-consecutive tiles: every tile writes the same values and the same norm
-partial either way, and the stop decision sums the partials in tile order,
-so sweeps, norms and iterates are bit-identical.  The 128^3 splits have
+consecutive tiles (in both cases each XCD sweeps its share of the tiles):
+every tile writes the same values and the same norm partial either way,
+and the stop decision sums the partials in tile order, so sweeps, norms and
+iterates are bit-identical.  The 128^3 splits have
 about twice as many tiles as the device holds workgroups at once, so the
 resident round really gives each workgroup several tiles."""
 import numpy as np
@@ -40,7 +41,8 @@ def test_grid_choices_are_bit_identical(lap128, name, mode, P, sub, auto_residen
         st, sw, rr = b.jac_solve(h, 1e-2, 3000)
         out[g] = (hist, x, int(sw[0]), float(rr[0]), get_x(h, s.n)[0])
         b.jac_destroy(h)
-    assert grids[1] == ntiles + 1
+    # a workgroup per tile: the XCD with the most tiles sets the count
+    assert ntiles + 1 <= grids[1] <= ntiles + ntiles // 4 + 9
     assert grids[2] < ntiles + 1                      # several tiles per workgroup
     assert grids[0] == (grids[2] if auto_resident else grids[1]), name
     for g in (2, 0):
