@@ -427,8 +427,10 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
 }
 
 // ---------------------------------------------------------------------------
-// One launch per sweep (single system).  Workgroups 0..ntiles-1 sweep one tile
-// each; the last workgroup takes the stop decision on the previous sweep.
+// One launch per sweep (single system).  All workgroups but the last sweep
+// tiles (each XCD its range of them: one tile per workgroup, or one resident
+// round of workgroups taking several each); the last workgroup takes the
+// stop decision on the previous sweep.
 // ---------------------------------------------------------------------------
 // The FP64 single right-hand-side sweep on the shift-table formats fits 8
 // waves per SIMD once some scalar registers spill to vector lanes (outside
