@@ -1,0 +1,106 @@
+// Host-only check of the split and sliced-layout planner (no GPU): builds the
+// 7-point Laplacian on an N^3 grid, splits it, plans the layout and decodes
+// every stored entry back from its slot, as the sweep kernel would, against
+// the permuted CSR.  Prints one summary line, or "FAIL ..." and exits 1.
+//
+// usage: host_plan_check N mode nparts [sub]   (mode 1 JB, 2 JBO, 3 JSS)
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "jac_internal.h"
+
+namespace jac {
+void fail(jac_status s, const std::string& msg) { throw Error{s, msg}; }
+void hip_check(hipError_t, const char*) {}
+void set_last_error(const std::string&) {}
+}  // namespace jac
+
+using namespace jac;
+
+static int bad(const char* what, long long a, long long b)
+{
+    printf("FAIL %s %lld %lld\n", what, a, b);
+    return 1;
+}
+
+int main(int argc, char** argv)
+{
+    if (argc < 4) return 2;
+    const int N = atoi(argv[1]), mode = atoi(argv[2]), P = atoi(argv[3]);
+    const int sg = argc > 4 ? atoi(argv[4]) : 2;
+    Csr a;
+    a.n = N * N * N;
+    a.rp.push_back(0);
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                const int r = x + N * (y + N * z);
+                const int nb[7] = {z > 0 ? r - N * N : -1, y > 0 ? r - N : -1, x > 0 ? r - 1 : -1, r,
+                                   x < N - 1 ? r + 1 : -1, y < N - 1 ? r + N : -1, z < N - 1 ? r + N * N : -1};
+                for (int c : nb)
+                    if (c >= 0) {
+                        a.ci.push_back(c);
+                        a.v.push_back(c == r ? 6.0 : -1.0);
+                    }
+                a.rp.push_back((int32_t)a.ci.size());
+            }
+    const int32_t grid[3] = {N, N, N}, sub[3] = {sg, sg, sg};
+    try {
+        Partition part = make_partition(a, mode, P, mode == JAC_SUBSTRUCT ? sub : nullptr, grid, 0);
+        std::vector<int64_t> src;
+        Csr pa = permute(a, part.perm, part.iperm, &src);
+        PlanParams prm;
+        prm.tile_rows = 512;
+        prm.lds_elems = 4096;
+        prm.staged = mode != JAC_BANDROW;
+        prm.tables = true;
+        const Plan pl = make_plan(pa, part.cuts, prm);
+        // slot -> (slice, slot column)
+        std::vector<int32_t> slice_of((size_t)pl.slots, -1), k_of((size_t)pl.slots, -1), tile_of(pl.nslices, -1);
+        for (int32_t t = 0; t < pl.ntiles; ++t)
+            for (int32_t s = pl.tile_slice0[t]; s < pl.tile_slice0[t + 1]; ++s) tile_of[s] = t;
+        for (int32_t s = 0; s < pl.nslices; ++s)
+            for (int32_t k = 0; k < pl.slice_width[s]; ++k)
+                for (int l = 0; l < kSlice; ++l) {
+                    const int64_t q = pl.slice_off[s] + (int64_t)k * kSlice + l;
+                    slice_of[q] = s;
+                    k_of[q] = k;
+                }
+        std::vector<char> used((size_t)pl.slots, 0);
+        const bool table = pl.colfmt == COL_TABG || pl.colfmt == COL_TABL;
+        for (int32_t i = 0; i < pa.n; ++i)
+            for (int32_t p = pa.rp[i]; p < pa.rp[i + 1]; ++p) {
+                const int64_t q = pl.slot_of_nnz[p];
+                if (q < 0 || q >= pl.slots) return bad("slot out of range", p, q);
+                if (used[q]++) return bad("slot used twice", p, q);
+                const int32_t s = slice_of[q], t = tile_of[s];
+                if (i - pl.slice_row0[s] != (int32_t)(q - pl.slice_off[s]) % kSlice) return bad("lane", i, q);
+                int32_t c;          // the column (or LDS position) the kernel reads
+                if (table) c = i + pl.shift[pl.slice_off[s] / kSlice + k_of[q]];
+                else if (pl.colfmt == COL_GLOBAL32) c = pl.col32[q];
+                else if (pl.colfmt == COL_REL16) c = i + (int16_t)pl.col16[q];
+                else c = pl.col16[q];
+                if (prm.staged) {   // LDS position -> global column through the tile's runs
+                    if (c < 0 || c >= pl.tile_fp[t]) return bad("LDS position", i, c);
+                    int32_t r = pl.tile_run0[t];
+                    while (r + 1 < pl.tile_run0[t + 1] && pl.run_lds[r + 1] <= c) ++r;
+                    c = pl.run_start[r] + (c - pl.run_lds[r]);
+                }
+                if (c != pa.ci[p]) return bad("column", p, c);
+                if (pa.ci[p] == i && pl.diag_slot[i] != q) return bad("diagonal slot", i, q);
+            }
+        for (int x = 0; x < 8; ++x)
+            if (pl.xcd_tile0[x] > pl.xcd_tile0[x + 1]) return bad("XCD ranges", x, pl.xcd_tile0[x]);
+        if (pl.xcd_tile0[0] != 0 || pl.xcd_tile0[8] != pl.ntiles) return bad("XCD ends", pl.xcd_tile0[8], pl.ntiles);
+        printf("fmt %d ntiles %d slots %lld spread %.4f xcd", pl.colfmt, pl.ntiles, (long long)pl.slots,
+               pl.tile_cost_spread);
+        for (int x = 0; x < 9; ++x) printf(" %d", pl.xcd_tile0[x]);
+        printf("\n");
+    } catch (Error& e) {
+        printf("FAIL error %d %s\n", (int)e.status, e.msg.c_str());
+        return 1;
+    }
+    return 0;
+}
