@@ -3,7 +3,9 @@
 // every stored entry back from its slot, as the sweep kernel would, against
 // the permuted CSR.  Prints one summary line, or "FAIL ..." and exits 1.
 //
-// usage: host_plan_check N mode nparts [sub]   (mode 1 JB, 2 JBO, 3 JSS)
+// usage: host_plan_check N mode nparts [sub [layout]]   (mode 1 JB, 2 JBO, 3 JSS;
+// layout: 0 the planner's choice, 1 no shift tables, 2 no shift tables and
+// global 32-bit columns for the unstaged split)
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -30,6 +32,7 @@ int main(int argc, char** argv)
     if (argc < 4) return 2;
     const int N = atoi(argv[1]), mode = atoi(argv[2]), P = atoi(argv[3]);
     const int sg = argc > 4 ? atoi(argv[4]) : 2;
+    const int layout = argc > 5 ? atoi(argv[5]) : 0;
     Csr a;
     a.n = N * N * N;
     a.rp.push_back(0);
@@ -55,7 +58,8 @@ int main(int argc, char** argv)
         prm.tile_rows = 512;
         prm.lds_elems = 4096;
         prm.staged = mode != JAC_BANDROW;
-        prm.tables = true;
+        prm.tables = layout == 0;
+        prm.rel16 = layout < 2;
         const Plan pl = make_plan(pa, part.cuts, prm);
         // slot -> (slice, slot column)
         std::vector<int32_t> slice_of((size_t)pl.slots, -1), k_of((size_t)pl.slots, -1), tile_of(pl.nslices, -1);

@@ -52,6 +52,14 @@ def test_every_entry_decodes_from_its_slot(checker, N, mode, P, sub, fmt):
     assert xcd[0] == 0 and xcd[8] == r["ntiles"] and all(u <= v for u, v in zip(xcd, xcd[1:]))
 
 
+@pytest.mark.parametrize("mode,layout,fmt", [(1, 1, 1), (1, 2, 0), (2, 1, 2), (3, 1, 2)])
+def test_explicit_column_formats_decode(checker, mode, layout, fmt):
+    # without shift tables: row-relative 16-bit columns (unstaged), 32-bit
+    # global ones when asked, tile-local 16-bit LDS positions (staged)
+    r = run(checker, 20, mode, 6, 2, layout)
+    assert r["fmt"] == fmt
+
+
 def test_tile_cost_spread_and_xcd_ranges(checker):
     jb = run(checker, 32, 1, 8, 2)
     jbo = run(checker, 32, 2, 8, 2)
