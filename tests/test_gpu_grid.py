@@ -61,3 +61,29 @@ def test_grid_option_range():
         b.jac_set_option(h, b.JAC_OPT_GRID, 3)
     assert b.jac_get_option(h, b.JAC_OPT_GRID) == 0
     b.jac_destroy(h)
+
+
+def test_adjoint_and_refinement_under_both_grids(lap128):
+    # the adjoint's forward and recompute sweeps and the FP32 inner sweeps run
+    # the same launches: several tiles per workgroup must not change a bit
+    need_gpu()
+    b = B()
+    s = lap128
+    import torch
+    rng = np.random.default_rng(11)
+    g = torch.from_numpy(rng.uniform(-1, 1, s.n)).cuda()
+    out = {}
+    for grid in (1, 2):
+        h = make(s, 1, 64, None, opts={b.JAC_OPT_GRID: grid})
+        gb = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        gv = torch.empty(s.nnz, dtype=torch.float64, device="cuda")
+        b.jac_adjoint(h, 12, 4, g, gb, gv)
+        torch.cuda.synchronize()
+        grads = (gb.cpu().numpy(), gv.cpu().numpy())
+        b.jac_set_x(h, None)
+        st, sw, rr = b.jac_solve(h, 1e-12, 600, b.JAC_NORM_L2_REL, b.JAC_FP32_REFINE)
+        out[grid] = (grads, int(sw[0]), float(rr[0]), get_x(h, s.n)[0], b.jac_get_info(h)["loop_grid"])
+        b.jac_destroy(h)
+    assert out[2][4] < out[1][4]
+    assert np.array_equal(out[1][0][0], out[2][0][0]) and np.array_equal(out[1][0][1], out[2][0][1])
+    assert out[1][1:3] == out[2][1:3] and np.array_equal(out[1][3], out[2][3])
