@@ -237,6 +237,8 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         }
     }
     if (prm.staged) pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+    // tile cost spread: streamed bytes (about 10 per slot, 8 per staged
+    // entry) plus 256 per footprint run, largest over mean
     {
         double sum = 0.0, mx = 0.0;
         for (int32_t t = 0; t < pl.ntiles; ++t) {
@@ -247,6 +249,8 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         }
         pl.tile_cost_spread = sum > 0.0 ? mx / (sum / pl.ntiles) : 1.0;
     }
+    // tile ranges of the eight XCDs: equal counts for alike tiles, else cut
+    // at equal shares of the prefix sum of streamed bytes
     {
         std::vector<double> pre((size_t)pl.ntiles + 1, 0.0);
         for (int32_t t = 0; t < pl.ntiles; ++t) {
