@@ -9,8 +9,14 @@ substructuring on an 8x8x8 subdomain grid grouped into 64 parts (JSS), with the
 residual 2-norm of every sweep recorded on the device.
 
 value = algorithmic bytes of all sweeps of the timed steps / their time, with
-the CSR byte model 12 nnz + 4 (n+1) + 32 n per sweep (values, columns, row
-pointers, x, b, D^{-1}, x').  Inputs are resident in HBM before timing starts.
+the lean byte model 12 nnz + 4 (n+1) + 24 n per sweep (values and int32
+columns, row pointers, b, x_k read and x_{k+1} written; the diagonal comes
+from the row's own values, so no D^{-1} vector is counted: the sweep kernels
+read none).  Inputs are resident in HBM before timing starts.  One 128^3
+sweep streams about 188 MiB, which the 256 MiB Infinity Cache keeps between
+sweeps: the headline is a cache-resident figure.  The HBM-bound control is
+the same Laplacian at 192^3 (727 MiB per sweep, matrix streamed) under the
+same three splits, reported as roofline_hbm.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -26,6 +32,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Jacobi sweep GB/s (% HBM peak) at 128^3 FP64; batched/adjoint/FP32 vs plain"
 HBM_PEAK_GBS = 8000.0
+BYTE_MODEL = ("lean: 12 nnz + 4 (n+1) + 24 n per sweep (values, int32 columns, row pointers, b and x_k read, "
+              "x_k+1 written; the diagonal is read with the row's values, no D^-1 vector)")
 
 
 def parse():
@@ -45,12 +53,22 @@ def parse():
     ap.add_argument("--lds-elems", type=int, default=0)
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the FP32-refinement, batched and adjoint comparisons")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound 192^3 control of the three splits")
+    ap.add_argument("--hbm-N", type=int, default=192, help="grid edge of the HBM-bound control")
+    ap.add_argument("--hbm-sweeps", type=int, default=200, help="sweeps per timed loop of the HBM-bound control")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the batched solve in one persistent (cooperative) launch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "launch.h")
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def src_digest():
@@ -63,29 +81,57 @@ def src_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_tag, launches_bytes):
-    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE
-    counters scaled by a copy-kernel calibration) from the committed counter
-    summary profiles/traffic.json, when it was taken on the current kernel
-    sources; else None."""
+def traffic_from_profile(kernel_tag, N):
+    """HBM-side bytes per launch of a sweep kernel on the N^3 Laplacian
+    (FETCH_SIZE and WRITE_SIZE counters scaled by a copy-kernel calibration)
+    from the committed counter summary profiles/traffic.json, when it was
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    rec = t.get(kernel_tag)
+    rec = t.get(f"{kernel_tag} @ {N}^3")
     if not rec or rec.get("src_digest") != src_digest():
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sysm, seconds):
-    """The oracle on the host cores: chunks of sweeps of the same system, each
-    continuing from the previous chunk's iterate, until about `seconds` of
-    CPU work have run; same byte model as the GPU figure."""
+def host_cpu():
+    """The host's CPU model, its logical CPU count, the CPUs this process may
+    run on, and the threads the oracle uses: the affinity set, capped by
+    OMP_NUM_THREADS when the machine sets it (a shared host gives each job a
+    share of its cores that way)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = nproc
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(affinity, int(omp)) if omp.isdigit() and int(omp) > 0 else affinity
+    return model, nproc, affinity, threads
+
+
+def cpu_baseline(sysm, seconds, batch16=None):
+    """The oracle on the host cores, same byte model as the GPU figure:
+    (1) all the threads this process may use, chunks of sweeps of the same
+    system, each continuing from the previous chunk's iterate, until about
+    `seconds` of CPU work have run; (2) one thread (the parity mode) for a few
+    sweeps; (3) the batched workload's seeded 16-system subset, every
+    right-hand side solved to 1e-8 with all threads."""
     from oracle import ref
-    from paper_2112_02377_amd.workloads import bytes_per_sweep
-    threads = min(16, os.cpu_count() or 1)
+    from paper_2112_02377_amd.workloads import lean_bytes_per_sweep
+    model, nproc, affinity, threads = host_cpu()
+    bps = lean_bytes_per_sweep(sysm.n, sysm.nnz)
     ref.sweeps(sysm.row_ptr, sysm.col_idx, sysm.vals, sysm.b[0], 2, threads=threads)
     chunk, done, x = 100, 0, None
     t0 = time.perf_counter()
@@ -95,11 +141,40 @@ def cpu_baseline(sysm, seconds):
         dt = time.perf_counter() - t0
         if dt >= seconds:
             break
-    return {"value": round(done * bytes_per_sweep(sysm.n, sysm.nnz) / dt / 1e9, 3), "unit": "GB/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{done} sweeps of the same {round(sysm.n ** (1 / 3))}^3 system from x0 = 0 in chunks of {chunk} "
-                      f"(residual norm per sweep), plain C FP64 oracle, {threads} OpenMP threads, {dt:.1f} s",
-            "sweeps_per_s": round(done / dt, 3)}
+    edge = round(sysm.n ** (1 / 3))
+    out = {"value": round(done * bps / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} sweeps of the same {edge}^3 system from x0 = 0 in chunks of {chunk} "
+                     f"(residual norm per sweep), plain C FP64 oracle, {threads} OpenMP threads, {dt:.1f} s; "
+                     f"lean byte model",
+           "sweeps_per_s": round(done / dt, 3), "cpu_model": model, "nproc": nproc, "affinity_cpus": affinity}
+    k1 = 20
+    t0 = time.perf_counter()
+    ref.sweeps(sysm.row_ptr, sysm.col_idx, sysm.vals, sysm.b[0], k1, threads=1)
+    dt = time.perf_counter() - t0
+    out["single_thread"] = {"GBps": round(k1 * bps / dt / 1e9, 3), "sweeps_per_s": round(k1 / dt, 3),
+                            "sample": f"{k1} sweeps of the {edge}^3 system, 1 thread (parity mode), {dt:.2f} s"}
+    if batch16:
+        t0 = time.perf_counter()
+        sweeps, byts = 0, 0
+        for s in batch16:
+            for c in range(s.b.shape[0]):
+                st, _, k, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[c], 1e-8, 1000000, threads=threads)
+                sweeps += k
+                byts += (k + 1) * lean_bytes_per_sweep(s.n, s.nnz)
+        dt = time.perf_counter() - t0
+        out["batched_subset16"] = {"s": round(dt, 3), "GBps": round(byts / dt / 1e9, 3), "column_sweeps": sweeps,
+                                   "sample": f"16 seeded systems of the batched workload (n total "
+                                             f"{sum(s.n for s in batch16)}), 4 right-hand sides each solved to "
+                                             f"relative 1e-8, {threads} OpenMP threads"}
+    return out
+
+
+def batch_subset16(systems):
+    """The seeded 16-system subset of the batched workload that the CPU
+    baseline solves (and the parity tests check against the oracle)."""
+    import numpy as np
+    pick = sorted(np.random.default_rng(2112).choice(len(systems), 16, replace=False).tolist())
+    return pick, [systems[i] for i in pick]
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):
@@ -133,7 +208,7 @@ def _timed(torch, stream, fn):
     return e0.elapsed_time(e1), r
 
 
-def secondary(B, W, torch, stream, with_oracle=True):
+def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
     """The comparisons the metric names, each against the plain FP64 sweep on
     the same GPU: FP32 inner sweeps with FP64 refinement (96^3 27-point
     FE-like matrix, to 1e-10), the batched persistent solve (256 diffusion
@@ -148,6 +223,7 @@ def secondary(B, W, torch, stream, with_oracle=True):
     import numpy as np
     out = {}
     sc = stream.cuda_stream
+    log("secondary: FP32 refinement")
     # -- FP32 refinement
     s = W.fe27(96, workload=3)
     h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
@@ -163,7 +239,21 @@ def secondary(B, W, torch, stream, with_oracle=True):
         B.jac_get_x(h, x)
         torch.cuda.synchronize()
         res[name] = dict(ms=round(ms, 3), sweeps=int(sw[0]), relres=float(rr[0]), x=x.cpu().numpy())
-    bytes64 = info["alg_bytes_per_sweep"]
+    # the autotuner's tile shape and inner stop parameters (tuning not timed)
+    B.jac_autotune(h, 20)
+    tuned = {"tile_rows": B.jac_get_option(h, B.JAC_OPT_TILE_ROWS), "block": B.jac_get_option(h, B.JAC_OPT_BLOCK),
+             "inner_tol": B.jac_get_option(h, B.JAC_OPT_INNER_TOL) * 1e-9,
+             "inner_max": B.jac_get_option(h, B.JAC_OPT_INNER_MAX)}
+    for prec, name in ((B.JAC_FP64, "fp64_tuned"), (B.JAC_FP32_REFINE, "fp32_refine_tuned")):
+        B.jac_set_x(h, None)
+        B.jac_solve(h, 1e-10, 100000, B.JAC_NORM_L2_REL, prec)      # warm
+        B.jac_set_x(h, None)
+        ms, (st, sw, rr) = _timed(torch, stream, lambda: B.jac_solve(h, 1e-10, 100000, B.JAC_NORM_L2_REL, prec))
+        x = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        B.jac_get_x(h, x)
+        torch.cuda.synchronize()
+        res[name] = dict(ms=round(ms, 3), sweeps=int(sw[0]), relres=float(rr[0]), x=x.cpu().numpy())
+    bytes64 = W.lean_bytes_per_sweep(s.n, s.nnz)
     bytes32 = 8 * info["nnz"] + 4 * (s.n + 1) + 16 * s.n
     ref_err = None
     if with_oracle:
@@ -182,9 +272,16 @@ def secondary(B, W, torch, stream, with_oracle=True):
         "speedup_vs_fp64": round(res["fp64"]["ms"] / res["fp32_refine"]["ms"], 3),
         "fp64_GBps": round(res["fp64"]["sweeps"] * bytes64 / res["fp64"]["ms"] / 1e6, 1),
         "inner_GBps_fp32_model": round(res["fp32_refine"]["sweeps"] * bytes32 / res["fp32_refine"]["ms"] / 1e6, 1),
+        "tuned": dict(tuned, fp64_ms=res["fp64_tuned"]["ms"], refine_ms=res["fp32_refine_tuned"]["ms"],
+                      refine_inner_sweeps=res["fp32_refine_tuned"]["sweeps"],
+                      refine_relres=res["fp32_refine_tuned"]["relres"],
+                      speedup_vs_fp64=round(res["fp64_tuned"]["ms"] / res["fp32_refine_tuned"]["ms"], 3)),
+        "default_inner": {"inner_tol": 1e-5, "inner_max": 256},
+        "byte_model": "FP64 sweep: lean (12 nnz + 4 (n+1) + 24 n); FP32 inner sweep: 8 nnz + 4 (n+1) + 16 n",
         "max_rel_err_vs_fp64_oracle": ref_err}
     B.jac_destroy(h)
     # -- batched
+    log("secondary: batched")
     systems = W.diffusion_batch(256, workload=4)
     hs = [B.jac_create(x.n, x.row_ptr, x.col_idx, x.vals, 4, x.b.reshape(-1), stream=sc) for x in systems]
     # 256 separate solves and the batched solve, both on the default tile
@@ -204,32 +301,44 @@ def secondary(B, W, torch, stream, with_oracle=True):
     B.jac_autotune_batched(hs, 32)
     t_tune = time.perf_counter() - t0
     shape = (B.jac_get_option(hs[0], B.JAC_OPT_TILE_ROWS), B.jac_get_option(hs[0], B.JAC_OPT_BLOCK))
-    B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 1)
-    ms_p, (st, swp, rrp) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
-    B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 0)
+    ms_p, swp = None, None
+    if persistent:
+        B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 1)
+        ms_p, (st, swp, rrp) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
+        B.jac_set_option(hs[0], B.JAC_OPT_LOOP, 0)
     for hh in hs:
         B.jac_set_x(hh, None)
     ms_b, (st, swb, rrb) = _timed(torch, stream, lambda: B.jac_solve_batched(hs, 1e-8, 1000000))
+    # the seeded 16-system subset the CPU baseline solves
+    pick, _ = batch_subset16(systems)
+    sub = [hs[i] for i in pick]
+    for hh in sub:
+        B.jac_set_x(hh, None)
+    ms_16, _ = _timed(torch, stream, lambda: B.jac_solve_batched(sub, 1e-8, 1000000))
     alg = 0
     for x, k in zip(systems, swb):
-        alg += (12 * x.nnz + 4 * (x.n + 1) + 8 * x.n + 96 * x.n) * (int(k[:4].max()) + 1)
+        alg += W.lean_bytes_per_sweep(x.n, x.nnz, 4) * (int(k[:4].max()) + 1)
     out["batched"] = {
         "workload": f"256 diffusion systems, edges U[16,64], n total {sum(x.n for x in systems)}, 4 rhs, tol 1e-8",
-        "batched_ms": round(ms_b, 3), "persistent_ms": round(ms_p, 3), "sequential_ms": round(ms_s, 3),
-        "batched_default_tiles_ms": round(ms_d, 3),
+        "batched_ms": round(ms_b, 3), "persistent_ms": None if ms_p is None else round(ms_p, 3),
+        "sequential_ms": round(ms_s, 3), "batched_default_tiles_ms": round(ms_d, 3),
+        "subset16_batched_ms": round(ms_16, 3), "subset16_systems": pick,
         "speedup_vs_sequential": round(ms_s / ms_b, 3), "max_sweeps": int(swb[:, :4].max()),
         "sum_system_sweeps": int(swb[:, :4].max(axis=1).sum()),
-        "batched_alg_GBps": round(alg / ms_b / 1e6, 1), "persistent_alg_GBps": round(alg / ms_p / 1e6, 1),
+        "byte_model": "lean, 4 right-hand sides: 12 nnz + 4 (n+1) + 96 n per system sweep",
+        "batched_alg_GBps": round(alg / ms_b / 1e6, 1),
+        "persistent_alg_GBps": None if ms_p is None else round(alg / ms_p / 1e6, 1),
         "sequential_alg_GBps": round(alg / ms_s / 1e6, 1),
         "sweep_counts_equal_to_separate_solves": bool(same),
         "tuned_vs_default_max_sweep_diff": int(np.abs(swb[:, :4] - swd[:, :4]).max()),
-        "persistent_equals_per_sweep_launches": bool(np.array_equal(swb, swp)),
+        "persistent_equals_per_sweep_launches": None if swp is None else bool(np.array_equal(swb, swp)),
         "tuned_tile_rows": int(shape[0]), "tuned_block": int(shape[1]), "tune_s": round(t_tune, 2),
         "note": "separate solves use the default tile shape (512 rows), the tuned batch the shape "
                 "jac_autotune_batched picked for the batch"}
     for hh in hs:
         B.jac_destroy(hh)
     # -- adjoint
+    log("secondary: adjoint")
     s = W.diffusion_adjoint(64, workload=5)
     h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
     gx = torch.from_numpy(s.extra["x_target"]).cuda()
@@ -247,7 +356,7 @@ def secondary(B, W, torch, stream, with_oracle=True):
     # (what the autograd Function does)
     ms_fc, _ = _timed(torch, stream, lambda: B.jac_sweep_checkpointed(h, 400, 20))
     ms_r, _ = _timed(torch, stream, lambda: B.jac_adjoint(h, 400, 20, gx, gb, gv))
-    fb = B.jac_get_info(h)["alg_bytes_per_sweep"]
+    fb = W.lean_bytes_per_sweep(s.n, s.nnz)
     # the same adjoint with checkpoints every 20 sweeps and recomputed
     # segments (a 200 MiB cap leaves no room for all 401 iterates)
     B.jac_set_option(h, B.JAC_OPT_CKPT_MEM_MB, 200)
@@ -265,7 +374,9 @@ def secondary(B, W, torch, stream, with_oracle=True):
                       "forward_GBps": round(400 * fb / ms_f / 1e6, 1)}
     B.jac_destroy(h)
     # -- the paper's Set-1 cubes (Q1 FE stand-ins) with its stop test
+    log("secondary: Set-1 cubes")
     out["paper_set1"] = set1(B, W, torch, stream)
+    log("secondary: partitioners, asynchronous, controls")
     # -- weighted partitions against equal-row bands
     out["partitions"] = partitions(B, W, torch, stream)
     # -- asynchronous relaxation against the synchronous solve
@@ -277,9 +388,8 @@ def secondary(B, W, torch, stream, with_oracle=True):
 
 def controls(B, W, torch, stream):
     """The 20^3 Laplacian solved to relative 1e-8 under each split (4 parts;
-    substructuring on 2x2x1 blocks), the 128^3 substructuring with one
-    subdomain per part (4x4x4 subdomains of 32^3, 64 parts), and the 192^3
-    band-row control (its band needs 32-bit column offsets)."""
+    substructuring on 2x2x1 blocks) and the 128^3 substructuring with one
+    subdomain per part (4x4x4 subdomains of 32^3, 64 parts)."""
     sc = stream.cuda_stream
     res = {}
     s = W.laplace7(20, workload=1)
@@ -297,8 +407,7 @@ def controls(B, W, torch, stream):
                     "sweeps_per_s": round(int(sw[0]) / (ms / 1e3), 1)}
     B.jac_destroy(h)
     res["laplace7_20_solve"] = c1
-    for name, N, mode, P, sub, K in (("laplace7_128_jss_4x4x4", 128, B.JAC_SUBSTRUCT, 64, (4, 4, 4), 500),
-                                     ("laplace7_192_jb", 192, B.JAC_BANDROW, 64, None, 200)):
+    for name, N, mode, P, sub, K in (("laplace7_128_jss_4x4x4", 128, B.JAC_SUBSTRUCT, 64, (4, 4, 4), 500),):
         s = W.laplace7(N, workload=2)
         h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
         B.jac_set_grid(h, N, N, N)
@@ -309,8 +418,9 @@ def controls(B, W, torch, stream):
         B.jac_sweep(h, K)
         info = B.jac_get_info(h)
         us = info["last_loop_ms"] * 1e3 / K
-        res[name] = {"us_per_sweep": round(us, 3), "GBps": round(info["alg_bytes_per_sweep"] / us / 1e3, 1),
-                     "pct_hbm_peak": round(100 * info["alg_bytes_per_sweep"] / us / 1e3 / HBM_PEAK_GBS, 2),
+        lb = W.lean_bytes_per_sweep(s.n, s.nnz)
+        res[name] = {"us_per_sweep": round(us, 3), "GBps": round(lb / us / 1e3, 1),
+                     "pct_hbm_peak": round(100 * lb / us / 1e3 / HBM_PEAK_GBS, 2),
                      "halo_entries": int(info["halo_entries"]), "col_bytes": int(info["col_bytes"]), "n": s.n,
                      "nnz": s.nnz, "matrix_loads": "kept" if info["keep_matrix"] else "streamed"}
         B.jac_destroy(h)
@@ -425,7 +535,7 @@ def set1(B, W, torch, stream):
                 B.jac_set_x(h, None)
                 ms, (st, sw, rr) = _timed(torch, stream, lambda: B.jac_solve(h, 1e-8, 100000, B.JAC_NORM_INF_ABS))
                 e = {"iters": int(sw[0]) + 1, "ms": round(ms, 3), "final_res_inf": float(rr[0]),
-                     "GBps": round((int(sw[0]) + 1) * info["alg_bytes_per_sweep"] / ms / 1e6, 1),
+                     "GBps": round((int(sw[0]) + 1) * W.lean_bytes_per_sweep(s.n, s.nnz) / ms / 1e6, 1),
                      "tile_rows": B.jac_get_option(h, B.JAC_OPT_TILE_ROWS),
                      "block": B.jac_get_option(h, B.JAC_OPT_BLOCK)}
                 if tuned:
@@ -436,6 +546,125 @@ def set1(B, W, torch, stream):
         res[PAPER_SET1[N]["name"] + "_standin"] = r
         B.jac_destroy(h)
     return res
+
+
+MODES = {"JB": (1, 64, None), "JBO": (2, 64, None), "JSS": (3, 64, (8, 8, 8))}
+
+
+def make_handles(B, s, N, sel, stream, args):
+    handles, infos, setup_s = {}, {}, {}
+    for m in sel:
+        mode, P, sub = MODES[m]
+        t0 = time.perf_counter()
+        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=stream.cuda_stream)
+        B.jac_set_option(h, B.JAC_OPT_LOOP, args.loop)
+        if args.tile_rows:
+            B.jac_set_option(h, B.JAC_OPT_TILE_ROWS, args.tile_rows)
+        if args.block:
+            B.jac_set_option(h, B.JAC_OPT_BLOCK, args.block)
+        if args.wg_per_cu:
+            B.jac_set_option(h, B.JAC_OPT_WG_PER_CU, args.wg_per_cu)
+        if args.lds_elems:
+            B.jac_set_option(h, B.JAC_OPT_LDS_ELEMS, args.lds_elems)
+        B.jac_set_grid(h, N, N, N)
+        B.jac_partition(h, mode, P, sub)
+        B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
+        setup_s[m] = time.perf_counter() - t0
+        handles[m] = h
+        infos[m] = B.jac_get_info(h)
+    return handles, infos, setup_s
+
+
+def run_steps(B, torch, stream, handles, sel, K, steps, warmup):
+    """`warmup` untimed then `steps` timed steps; a step sweeps every split K
+    times from x0 = 0 with the residual norm of each sweep recorded.  Returns
+    (total ms by HIP events on the handles' stream, per-split loop ms of each
+    timed step, wall s)."""
+    hist = torch.zeros(K, dtype=torch.float64, device="cuda")
+    loop_ms = {m: [] for m in sel}
+
+    def step(record):
+        for m in sel:
+            B.jac_set_x(handles[m], None)
+            B.jac_sweep(handles[m], K, hist)
+            if record:
+                loop_ms[m].append(B.jac_get_info(handles[m])["last_loop_ms"])
+
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step(False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step(True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), loop_ms, wall
+
+
+def split_report(W, B, s, N, sel, infos, loop_ms, setup_s, K, loop):
+    """Per-split figures and the roofline of every sweep kernel of the step,
+    the dominant one (most time per step) first.  One launch is one sweep."""
+    lean = W.lean_bytes_per_sweep(s.n, s.nnz)
+    per_mode = {}
+    for m in sel:
+        avg = sum(loop_ms[m]) / len(loop_ms[m])
+        gbs = lean * K / (avg / 1e3) / 1e9
+        i = infos[m]
+        med = sorted(loop_ms[m])[len(loop_ms[m]) // 2]
+        per_mode[m] = {"loop_ms": round(avg, 3), "loop_ms_median": round(med, 3), "us_per_sweep": round(avg * 1e3 / K, 3),
+                       "sweeps_per_s": round(K / (avg / 1e3), 1), "GBps": round(gbs, 1),
+                       "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                       "csr_model_GBps": round(i["alg_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
+                       "dev_GBps": round(i["dev_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
+                       "dev_bytes_per_sweep": i["dev_bytes_per_sweep"],
+                       "col_bytes": i["col_bytes"], "col_format": i["col_format"], "halo_entries": i["halo_entries"],
+                       "staged_entries": i["staged_entries"], "ntiles": i["ntiles"], "grid": i["loop_grid"],
+                       "matrix_loads": "kept" if i["keep_matrix"] else "streamed", "setup_s": round(setup_s[m], 2)}
+    kern = {}
+    for m in sel:
+        kname = "k_loop" if loop else "k_sweep"
+        cm = infos[m]["col_format"]
+        nt = "false" if infos[m]["keep_matrix"] else "true"       # nontemporal matrix loads
+        kern.setdefault(f"{kname}<double, 1, {cm}, {nt}>", []).append(m)
+    order = sorted(kern, key=lambda t: -sum(per_mode[m]["loop_ms"] for m in kern[t]))
+    rows = []
+    for t in order:
+        ms_l = sum(per_mode[m]["loop_ms"] for m in kern[t]) / len(kern[t]) / K
+        rows.append({"kernel": t, "modes": kern[t], "avg_launch_ms": round(ms_l, 5), "alg_bytes_per_launch": lean,
+                     "achieved": round(lean / (ms_l / 1e3) / 1e9, 1),
+                     "frac": round(lean / (ms_l / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(t, N)})
+    dom = rows[0]
+    roof = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac"],
+            "traffic": dom["traffic"], "kernel": dom["kernel"], "modes": dom["modes"],
+            "alg_bytes_per_launch": lean, "avg_launch_ms": dom["avg_launch_ms"], "model": BYTE_MODEL,
+            "kernels": rows}
+    return per_mode, roof
+
+
+def hbm_bound(B, W, torch, stream, args):
+    """The three splits on the N^3 Laplacian (default 192^3: 727 MiB per
+    sweep, more than the Infinity Cache holds, so the matrix is streamed from
+    HBM every sweep), 64 parts each (substructuring: 8x8x8 subdomains of
+    24^3), timed like the headline with fewer sweeps."""
+    N, K = args.hbm_N, args.hbm_sweeps
+    s = W.laplace7(N, workload=2)
+    sel = list(MODES)
+    handles, infos, setup_s = make_handles(B, s, N, sel, stream, args)
+    _, loop_ms, _ = run_steps(B, torch, stream, handles, sel, K, 3, 1)
+    per_mode, roof = split_report(W, B, s, N, sel, infos, loop_ms, setup_s, K, args.loop)
+    for h in handles.values():
+        B.jac_destroy(h)
+    roof["workload"] = (f"laplace7 {N}^3 FP64 (n={s.n}, nnz={s.nnz}), {K} sweeps x (JB+JBO+JSS), 64 parts each "
+                        f"(JSS: 8x8x8 subdomains)")
+    roof["regime"] = (f"HBM-bound: one sweep streams {per_mode['JB']['dev_bytes_per_sweep'] / 2**20:.0f} MiB or more, "
+                      f"above the 256 MiB Infinity Cache; matrix loads nontemporal")
+    return per_mode, roof
 
 
 def main():
@@ -461,117 +690,50 @@ def main():
     N, K = args.N, args.sweeps
     s = W.laplace7(N, workload=2)
     stream = torch.cuda.Stream()
-    modes = {"JB": (B.JAC_BANDROW, 64, None), "JBO": (B.JAC_BANDROW_SP, 64, None),
-             "JSS": (B.JAC_SUBSTRUCT, 64, (8, 8, 8))}
     sel = [m for m in args.modes.split(",") if m]
-    handles, infos, setup_s = {}, {}, {}
-    for m in sel:
-        mode, P, sub = modes[m]
-        t0 = time.perf_counter()
-        h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=stream.cuda_stream)
-        B.jac_set_option(h, B.JAC_OPT_LOOP, args.loop)
-        if args.tile_rows:
-            B.jac_set_option(h, B.JAC_OPT_TILE_ROWS, args.tile_rows)
-        if args.block:
-            B.jac_set_option(h, B.JAC_OPT_BLOCK, args.block)
-        if args.wg_per_cu:
-            B.jac_set_option(h, B.JAC_OPT_WG_PER_CU, args.wg_per_cu)
-        if args.lds_elems:
-            B.jac_set_option(h, B.JAC_OPT_LDS_ELEMS, args.lds_elems)
-        B.jac_set_grid(h, N, N, N)
-        B.jac_partition(h, mode, P, sub)
-        B.jac_set_option(h, B.JAC_OPT_TIMING, 1)
-        torch.cuda.synchronize()
-        setup_s[m] = time.perf_counter() - t0
-        handles[m] = h
-        infos[m] = B.jac_get_info(h)
-    hist = torch.zeros(K, dtype=torch.float64, device="cuda")
-    loop_ms = {m: [] for m in sel}
-
-    def step(record):
-        for m in sel:
-            B.jac_set_x(handles[m], None)
-            B.jac_sweep(handles[m], K, hist)
-            if record:
-                loop_ms[m].append(B.jac_get_info(handles[m])["last_loop_ms"])
-
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step(False)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step(True)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    alg = {m: infos[m]["alg_bytes_per_sweep"] for m in sel}
-    total_bytes = args.steps * K * sum(alg.values())
+    handles, infos, setup_s = make_handles(B, s, N, sel, stream, args)
+    torch.cuda.synchronize()
+    log(f"{N}^3 splits {sel} set up; timing {args.steps} steps of {K} sweeps each")
+    ms_total, loop_ms, wall = run_steps(B, torch, stream, handles, sel, K, args.steps, args.warmup)
+    log(f"timed steps done: {ms_total / args.steps:.3f} ms per step")
+    lean = W.lean_bytes_per_sweep(s.n, s.nnz)
+    total_bytes = args.steps * K * lean * len(sel)
     value = total_bytes / (ms_total / 1e3) / 1e9
     for m in sel:
         infos[m] = B.jac_get_info(handles[m])
-    per_mode = {}
-    for m in sel:
-        avg = sum(loop_ms[m]) / len(loop_ms[m])
-        gbs = alg[m] * K / (avg / 1e3) / 1e9
-        i = infos[m]
-        med = sorted(loop_ms[m])[len(loop_ms[m]) // 2]
-        per_mode[m] = {"loop_ms": round(avg, 3), "loop_ms_median": round(med, 3), "us_per_sweep": round(avg * 1e3 / K, 3),
-                       "sweeps_per_s": round(K / (avg / 1e3), 1), "GBps": round(gbs, 1),
-                       "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
-                       "dev_GBps": round(i["dev_bytes_per_sweep"] * K / (avg / 1e3) / 1e9, 1),
-                       "col_bytes": i["col_bytes"], "halo_entries": i["halo_entries"],
-                       "staged_entries": i["staged_entries"], "ntiles": i["ntiles"], "grid": i["loop_grid"],
-                       "matrix_loads": "kept" if i["keep_matrix"] else "streamed", "setup_s": round(setup_s[m], 2)}
-    # dominant kernel: the loop instantiation with the most time per step
-    kern = {}
-    for m in sel:
-        kname = "k_loop" if args.loop else "k_sweep"
-        cm = infos[m]["col_format"]
-        nt = "false" if infos[m]["keep_matrix"] else "true"       # nontemporal matrix loads
-        tag = f"{kname}<double, 1, {cm}, {nt}>"
-        kern.setdefault(tag, []).append(m)
-    dom = max(kern, key=lambda t: sum(per_mode[m]["loop_ms"] for m in kern[t]))
-    dm = kern[dom]
-    # one launch of the sweep kernel is one sweep
-    avg_launch_ms = sum(per_mode[m]["loop_ms"] for m in dm) / len(dm) / K
-    bytes_launch = sum(alg[m] for m in dm) / len(dm)
-    achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, bytes_launch),
-            "kernel": dom, "modes": dm, "alg_bytes_per_launch": int(bytes_launch),
-            "avg_launch_ms": round(avg_launch_ms, 5)}
-    # every sweep kernel of the step, the dominant one first
-    per_kernel = []
-    for t in sorted(kern, key=lambda t: -sum(per_mode[m]["loop_ms"] for m in kern[t])):
-        ms_l = sum(per_mode[m]["loop_ms"] for m in kern[t]) / len(kern[t]) / K
-        b_l = sum(alg[m] for m in kern[t]) / len(kern[t])
-        per_kernel.append({"kernel": t, "modes": kern[t], "avg_launch_ms": round(ms_l, 5),
-                           "achieved": round(b_l / (ms_l / 1e3) / 1e9, 1),
-                           "frac": round(b_l / (ms_l / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "traffic": traffic_from_profile(t, b_l)})
-    roof["kernels"] = per_kernel
+    per_mode, roof = split_report(W, B, s, N, sel, infos, loop_ms, setup_s, K, args.loop)
+    stream_mib = max(per_mode[m]["dev_bytes_per_sweep"] for m in sel) / 2**20
+    roof["regime"] = (f"Infinity-Cache-resident: one sweep streams at most {stream_mib:.0f} MiB, which the 256 MiB "
+                      f"Infinity Cache keeps between sweeps (matrix loads temporal); see roofline_hbm for the "
+                      f"HBM-bound control")
+    csr_bytes = args.steps * K * sum(infos[m]["alg_bytes_per_sweep"] for m in sel)
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"laplace7 {N}^3 FP64, {K} sweeps x ({'+'.join(sel)}), 64 parts each "
                                   f"(JSS: 8x8x8 subdomains)", "n": s.n, "nnz": s.nnz, "sweeps": K,
-                      "parallelism": "1 GPU", "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+                      "parallelism": "1 GPU", "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+                      "byte_model": BYTE_MODEL,
+                      "csr_model_GBps": round(csr_bytes / (ms_total / 1e3) / 1e9, 1)},
            "roofline": roof, "modes": per_mode, "wall_s": round(wall, 3)}
     for h in handles.values():
         B.jac_destroy(h)
+    if not args.no_hbm:
+        log(f"HBM-bound control {args.hbm_N}^3")
+        out["hbm_modes"], out["roofline_hbm"] = hbm_bound(B, W, torch, stream, args)
+        log("HBM-bound control done")
     # the traffic the kernels stream (dev_GBps) beside a plain device copy's rate
     out["copy_GBps"] = copy_bandwidth(torch)
     for m in sel:
         per_mode[m]["pct_of_copy"] = round(100 * per_mode[m]["dev_GBps"] / out["copy_GBps"], 1)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        log("CPU oracle baseline")
+        _, sub16 = batch_subset16(W.diffusion_batch(256, workload=4))
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, sub16)
+        log("CPU oracle baseline done")
     if not args.no_secondary:
-        out["secondary"] = secondary(B, W, torch, stream, with_oracle=not args.no_cpu)
+        out["secondary"] = secondary(B, W, torch, stream, with_oracle=not args.no_cpu,
+                                     persistent=not args.no_persistent)
     print(json.dumps(out), flush=True)
 
 

@@ -79,7 +79,11 @@ typedef enum {
 typedef enum {
     JAC_OPT_TILE_ROWS = 1,   /* max rows per tile (multiple of 64), default 512     */
     JAC_OPT_BLOCK = 2,       /* threads per workgroup: 64..512, multiple of 64       */
-    JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096   */
+    JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096;
+                                the split bounds it further so that a tile's
+                                staged footprint (nrhs doubles per entry), its
+                                runs and the reduction scratch fit the device's
+                                LDS per workgroup (160 KiB on gfx950)          */
     JAC_OPT_LOOP = 4,        /* 0 = one launch per sweep (default), 1 = persistent
                                 cooperative loop with a grid barrier per sweep     */
     JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU (0 = occupancy)  */
@@ -162,9 +166,15 @@ typedef struct {
  * Columns must be strictly ascending within each row and every diagonal must
  * be present and nonzero (JAC_E_ZERO_DIAG), otherwise JAC_E_INVALID.
  * hip_stream: the hipStream_t all device work is ordered on (NULL = default).
- * D^{-1} is formed once here, one rounding per entry (section 3, vectorial
- * algorithm).  The new handle has x = 0 and an implicit JAC_BANDROW split
- * into one part.  nrhs must be 1, 2 or 4. */
+ * D^{-1} (section 3, vectorial algorithm: formed once before the
+ * iterations) is formed here as a vector, one correctly rounded division per
+ * row, for the adjoint and the FP32 refinement.  The sweep kernels do not
+ * read that vector: each recomputes 1/a_ii from the diagonal entry it loads
+ * with the row, by the same correctly rounded division, so it uses the
+ * identical value without streaming n more doubles per sweep.
+ * The new handle has x = 0 and an implicit JAC_BANDROW split into one part.
+ * nrhs must be 1, 2 or 4 (the kernels are instantiated for those counts;
+ * more right-hand sides take several handles, e.g. in jac_solve_batched). */
 jac_status jac_create(int32_t n, const int32_t *row_ptr_host, const int32_t *col_idx_host,
                       const double *vals_host, int32_t nrhs, const double *b_host, int32_t index_base,
                       void *hip_stream, jac_handle *out);

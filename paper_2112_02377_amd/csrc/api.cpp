@@ -73,6 +73,31 @@ Handle::~Handle()
     if (pev) (void)hipEventDestroy(pev);
 }
 
+// Compute units and LDS bytes per workgroup of the current device (queried
+// once; the initialisation of a function-local static is thread-safe, and
+// retried if it throws).
+static int num_cus()
+{
+    static const int cus = [] {
+        int dev = 0, n = 0;
+        JAC_HIP(hipGetDevice(&dev));
+        JAC_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        return n;
+    }();
+    return cus;
+}
+
+static int max_lds_bytes()
+{
+    static const int bytes = [] {
+        int dev = 0, n = 0;
+        JAC_HIP(hipGetDevice(&dev));
+        JAC_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        return n;
+    }();
+    return bytes;
+}
+
 // Rebuild the split and the sliced layout; keeps values, b and x.
 void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
 {
@@ -88,7 +113,15 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     Csr pa = permute(a, np.perm, np.iperm, &src);
     PlanParams prm;
     prm.tile_rows = opt.tile_rows;
-    prm.lds_elems = opt.lds_elems;
+    // a staged tile's LDS holds its footprint (nrhs doubles per entry), two
+    // words per footprint run and the reduction scratch: bound the footprint
+    // so that the largest tile still fits one workgroup's LDS (a tile over
+    // the bound is split, down to single slices, or the plan goes unstaged)
+    {
+        const int64_t avail = (int64_t)max_lds_bytes() - 8 * (int64_t)prm.max_runs - 1024;
+        const int64_t cap = std::max<int64_t>(avail / (8 * (int64_t)nrhs), kSlice);
+        prm.lds_elems = (int32_t)std::min<int64_t>(opt.lds_elems, cap);
+    }
     prm.staged = (mode != JAC_BANDROW);
     prm.tables = opt.tables != 0;
     Plan pl = make_plan(pa, np.cuts, prm);
@@ -274,18 +307,6 @@ int Handle::lds_fp_bytes(bool fp32) const
 
 int Handle::lds_runs() const { return plan.prm.staged ? std::max(plan.max_runs, 1) : 0; }
 
-// Compute units of the current device (queried once; the initialisation of a
-// function-local static is thread-safe, and retried if it throws).
-static int num_cus()
-{
-    static const int cus = [] {
-        int dev = 0, n = 0;
-        JAC_HIP(hipGetDevice(&dev));
-        JAC_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
-        return n;
-    }();
-    return cus;
-}
 
 // Workgroups of a one-launch-per-sweep k_sweep of the handle's system, the
 // deciding one included.  A workgroup per tile lets the dispatcher balance

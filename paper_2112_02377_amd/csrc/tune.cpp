@@ -1,7 +1,11 @@
 // Autotuner: times candidate tile shapes (rows per tile) and workgroup sizes
 // for the fused sweep on the handle's own matrix and split, keeps the fastest,
-// and caches the choice in a text file named by $JAC_TUNE_CACHE, one line per
-// key "n nnz nrhs mode nparts sx sy sz fp32" -> "tile_rows block us_per_sweep".
+// then times candidate inner stop parameters of the FP32 refinement (inner
+// relative tolerance tau and sweep cap m_max) on the tuned shape and keeps
+// the pair that reduces the FP64 residual fastest.  The choices are cached in
+// a text file named by $JAC_TUNE_CACHE, one line per key
+// "n nnz nrhs mode nparts sx sy sz fp32" -> "tile_rows block us_per_sweep",
+// and "refine <key>" -> "tau_x1e9 m_max decades_per_ms".
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -10,6 +14,9 @@
 #include <sstream>
 #include <string>
 #include <vector>
+
+#include <algorithm>
+#include <cmath>
 
 #include "handle.h"
 #include "launch.h"
@@ -35,7 +42,8 @@ std::string cache_key(const Handle& h)
     return k.str();
 }
 
-bool cache_lookup(const std::string& key, int32_t& rows, int32_t& block)
+// Two integers and a score stored for `key`; the last entry for a key wins.
+bool cache_lookup(const std::string& key, int64_t& a, int64_t& b)
 {
     const char* path = std::getenv("JAC_TUNE_CACHE");
     if (!path || !*path) return false;
@@ -47,19 +55,24 @@ bool cache_lookup(const std::string& key, int32_t& rows, int32_t& block)
         const size_t bar = line.find('|');
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream v(line.substr(bar + 1));
-        double us = 0;
-        if (v >> rows >> block >> us) found = true;     // the last entry for a key wins
+        int64_t x = 0, y = 0;
+        double score = 0;
+        if (v >> x >> y >> score) {
+            a = x;
+            b = y;
+            found = true;
+        }
     }
     return found;
 }
 
-void cache_store(const std::string& key, int32_t rows, int32_t block, double us)
+void cache_store(const std::string& key, int64_t a, int64_t b, double score)
 {
     const char* path = std::getenv("JAC_TUNE_CACHE");
     if (!path || !*path) return;
     std::lock_guard<std::mutex> lock(g_cache_mutex);
     std::ofstream f(path, std::ios::app);
-    f << key << '|' << rows << ' ' << block << ' ' << us << '\n';
+    f << key << '|' << a << ' ' << b << ' ' << score << '\n';
 }
 
 // Average duration of `sweeps` fixed sweeps (after two unrecorded ones), ms.
@@ -78,6 +91,72 @@ double time_sweeps(Handle& h, int32_t sweeps)
     return h.last_loop_ms;
 }
 
+// Inner stop parameters of the FP32 refinement: relative tolerance (x1e-9)
+// and sweep cap.  Every pair runs one trial: a refinement from x = 0 with
+// tolerance 0 (so it ends at the sweep budget or when the FP64 residual
+// stops falling), scored by decades of FP64 residual reduction per
+// millisecond.  Too loose a tau spends FP64 residuals and host round trips on
+// many outer steps; too tight a tau, or too large a cap on a slowly converging
+// system, spends FP32 sweeps below what FP32 rounding lets the correction
+// reach.
+const int64_t kTauE9[] = {1000000, 100000, 10000, 1000};
+const int32_t kInnerMax[] = {64, 256, 1024, 4096};
+
+void tune_refine(Handle& h, int32_t sweeps_per_trial, const std::string& key)
+{
+    int64_t tau = 0, mmax = 0;
+    if (cache_lookup("refine " + key, tau, mmax)) {
+        h.opt.inner_tol = (double)tau * 1e-9;
+        h.opt.inner_max = (int32_t)mmax;
+        return;
+    }
+    const int32_t budget = std::max<int32_t>(16 * sweeps_per_trial, 1024);
+    const double tol0 = h.opt.inner_tol;
+    const int32_t max0 = h.opt.inner_max;
+    for (auto& e : h.ev)
+        if (!e) JAC_HIP(hipEventCreate(&e));
+    const int32_t timing = h.opt.timing;
+    h.opt.timing = 0;
+    double best = -1.0;
+    int64_t pick_tau = (int64_t)std::llround(tol0 * 1e9);
+    int32_t pick_max = max0;
+    for (int64_t t : kTauE9)
+        for (int32_t m : kInnerMax) {
+            h.opt.inner_tol = (double)t * 1e-9;
+            h.opt.inner_max = m;
+            JAC_HIP(hipMemsetAsync(h.d.x0.p, 0, (size_t)h.a.n * h.nrhs * sizeof(double), h.stream));
+            h.sync();
+            JAC_HIP(hipEventRecord(h.ev[0], h.stream));
+            double rel[4] = {0, 0, 0, 0};
+            jac_status st = JAC_OK;
+            try {
+                st = solve_refine(h, 0.0, budget, JAC_NORM_L2_REL, nullptr, rel);
+            } catch (const Error& e) {
+                if (e.status != JAC_E_DIVERGED) throw;
+                st = JAC_E_DIVERGED;      // a pair that diverges is not a candidate
+            }
+            JAC_HIP(hipEventRecord(h.ev[1], h.stream));
+            JAC_HIP(hipEventSynchronize(h.ev[1]));
+            float ms = 0.f;
+            JAC_HIP(hipEventElapsedTime(&ms, h.ev[0], h.ev[1]));
+            if (st < 0) continue;
+            // the worst right-hand side decides; x = 0 starts at relative 1
+            double worst = 0.0;
+            for (int c = 0; c < h.nrhs; ++c) worst = std::max(worst, rel[c]);
+            const double decades = -std::log10(std::max(worst, 1e-300));
+            const double score = decades / std::max((double)ms, 1e-6);
+            if (score > best) {
+                best = score;
+                pick_tau = t;
+                pick_max = m;
+            }
+        }
+    h.opt.timing = timing;
+    h.opt.inner_tol = (double)pick_tau * 1e-9;
+    h.opt.inner_max = pick_max;
+    cache_store("refine " + key, pick_tau, pick_max, best);
+}
+
 }  // namespace
 }  // namespace jac
 
@@ -93,42 +172,46 @@ extern "C" jac_status jac_autotune(jac_handle hp, int32_t sweeps_per_trial)
         ++h.state_gen;
         const std::string key = cache_key(h);
         const int32_t* sub = h.part_has_sub ? h.part_sub : nullptr;
-        int32_t rows = 0, block = 0;
-        if (cache_lookup(key, rows, block)) {
-            h.opt.block = block;
-            if (rows != h.opt.tile_rows) {
-                h.opt.tile_rows = rows;
-                h.replan(h.part_mode, h.part_nparts, sub);
-            }
-            return JAC_OK;
-        }
         // keep the caller's iterate across the trials
         DevMem xs;
         xs.alloc((size_t)h.a.n * h.nrhs * sizeof(double));
         h.get_x_dev(static_cast<double*>(xs.p));
-        double best = 1e300;
-        Cand pick = {h.opt.tile_rows, h.opt.block};
-        for (const Cand& c : kCands) {
-            if (c.tile_rows != h.opt.tile_rows) {
-                h.opt.tile_rows = c.tile_rows;
+        int64_t rows = 0, block = 0;
+        if (cache_lookup(key, rows, block)) {
+            h.opt.block = (int32_t)block;
+            if (rows != h.opt.tile_rows) {
+                h.opt.tile_rows = (int32_t)rows;
                 h.replan(h.part_mode, h.part_nparts, sub);
             }
-            h.opt.block = c.block;
-            const double ms = time_sweeps(h, sweeps_per_trial);
-            if (ms < best) {
-                best = ms;
-                pick = c;
+        } else {
+            double best = 1e300;
+            Cand pick = {h.opt.tile_rows, h.opt.block};
+            for (const Cand& c : kCands) {
+                if (c.tile_rows != h.opt.tile_rows) {
+                    h.opt.tile_rows = c.tile_rows;
+                    h.replan(h.part_mode, h.part_nparts, sub);
+                }
+                h.opt.block = c.block;
+                const double ms = time_sweeps(h, sweeps_per_trial);
+                if (ms < best) {
+                    best = ms;
+                    pick = c;
+                }
             }
+            h.opt.block = pick.block;
+            if (pick.tile_rows != h.opt.tile_rows) {
+                h.opt.tile_rows = pick.tile_rows;
+                h.replan(h.part_mode, h.part_nparts, sub);
+            }
+            cache_store(key, pick.tile_rows, pick.block, best * 1e3 / sweeps_per_trial);
         }
-        h.opt.block = pick.block;
-        if (pick.tile_rows != h.opt.tile_rows) {
-            h.opt.tile_rows = pick.tile_rows;
-            h.replan(h.part_mode, h.part_nparts, sub);
-        }
+        tune_refine(h, sweeps_per_trial, key);
+        // the refinement trials left their residual in the norm partials and
+        // their iterates in x: restore the caller's x (the partials of the
+        // next loop are rewritten before they are read)
         launch_gather_in(static_cast<const double*>(xs.p), static_cast<const int32_t*>(h.d.perm.p), h.a.n, h.nrhs,
                          static_cast<double*>(h.d.x0.p), h.stream);
         h.sync();
-        cache_store(key, pick.tile_rows, pick.block, best * 1e3 / sweeps_per_trial);
         return JAC_OK;
     });
 }
@@ -167,9 +250,9 @@ extern "C" jac_status jac_autotune_batched(const jac_handle* hs, int32_t nsys, i
                 }
             }
         };
-        int32_t rows = 0, block = 0;
+        int64_t rows = 0, block = 0;
         if (cache_lookup(key, rows, block)) {
-            apply(rows, block);            // re-planning keeps every system's x
+            apply((int32_t)rows, (int32_t)block);   // re-planning keeps every system's x
             return JAC_OK;
         }
         // keep every system's iterate across the trials

@@ -317,3 +317,10 @@ def bytes_per_sweep(n: int, nnz: int) -> int:
     columns (12 per entry), row pointers (4 per row + 1), and x, b, invD read
     plus x' written (32 per row)."""
     return 12 * nnz + 4 * (n + 1) + 32 * n
+
+
+def lean_bytes_per_sweep(n: int, nnz: int, nrhs: int = 1) -> int:
+    """The same without a D^-1 vector (the diagonal is taken from the row's
+    own values): 12 per entry, 4 per row + 1, and b, x read plus x' written
+    (24 per row and right-hand side)."""
+    return 12 * nnz + 4 * (n + 1) + 24 * n * nrhs

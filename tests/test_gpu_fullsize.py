@@ -3,9 +3,8 @@
 The 128^3 7-point Laplacian (n = 2,097,152, b = A x* as in the bench), 64
 parts under each split, the bench's default tile shape and loop:
 
-* one sweep from the device's own state x_k, checked on sampled rows (random
-  rows plus the first and last row of every part) against the oracle's
-  single-row sweep from the same x_k: the per-sweep bar, 1e-12 relative;
+* one sweep from the device's own state x_k, every row of x_{k+1} against
+  the oracle's sweep from the same x_k: the per-sweep bar, 1e-12 relative;
 * 2000 sweeps from x_0 = 0 against the oracle's 2000 sweeps.  The two sum
   each row in a different rounding (fused multiply-add on the device, and the
   substructured order permutes columns), so they drift apart by at most the
@@ -20,13 +19,18 @@ parts under each split, the bench's default tile shape and loop:
 * the 96^3 27-point FE-like system of the refinement comparison: FP64 and
   FP32-inner solves to 1e-10 against the oracle's FP64 solve;
 * the 256-system, 4-right-hand-side batch of the batched comparison: every
-  column against its system solved alone, and 8 systems against the oracle
-  column by column."""
+  column bit-identical to its system solved alone and its FP64 residual
+  recomputed on the host; a seeded subset of 16 systems plus the smallest and
+  the largest against the oracle column by column (stop sweep exact, iterate
+  within 1e-10)."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from gpu_util import B, get_x, make, need_gpu, rel_inf, sweep
+from gpu_util import B, get_x, make, need_gpu, rel_inf, sweep, torch
+from oracle import partition as OP
 from oracle import ref
 from paper_2112_02377_amd import workloads as W
 
@@ -48,15 +52,8 @@ def ref_sweeps(s, K):
     return _REF[K]
 
 
-def sample_rows(s, h, rng):
-    got = B().jac_get_partition(h)
-    perm, bounds = got["perm"], got["bounds"]
-    edges = [int(perm[r]) for r in bounds[:-1] if r < s.n] + [int(perm[r - 1]) for r in bounds[1:] if r > 0]
-    return np.unique(np.concatenate([rng.choice(s.n, 4096, replace=False), edges, [0, s.n - 1]])).astype(np.int32)
-
-
 @pytest.mark.parametrize("mode,P,sub", MODES)
-def test_one_sweep_from_device_state_on_sampled_rows(big, mode, P, sub):
+def test_one_sweep_from_device_state_every_row(big, mode, P, sub):
     need_gpu()
     b = B()
     s = big
@@ -65,11 +62,11 @@ def test_one_sweep_from_device_state_on_sampled_rows(big, mode, P, sub):
     xk = get_x(h, s.n)[0]
     hist = sweep(h, 1)[:, 0]
     xk1 = get_x(h, s.n)[0]
-    rows = sample_rows(s, h, np.random.default_rng(mode))
-    st, xr, _ = ref.sweep_rows(s.row_ptr, s.col_idx, s.vals, s.b[0], xk, rows)
+    st, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], 1, x0=xk, threads=16)
     assert st == ref.OK
     scale = max(np.abs(xk1).max(), 1.0)
-    assert np.abs(xk1[rows] - xr).max() <= 1e-12 * scale
+    assert np.abs(xk1 - xr).max() <= 1e-12 * scale
+    assert abs(hist[0] - hr[0]) <= 1e-12 * hr[0]
     # the recorded norm is that of b - A x_k
     r = np.linalg.norm(s.b[0] - s.scipy() @ xk)
     assert abs(hist[0] - r) <= 1e-12 * r
@@ -141,6 +138,13 @@ def test_fe27_96_fp64_and_fp32_refinement_at_full_size():
     assert np.abs(x - xo).max() / np.abs(xo).max() <= 1e-9
 
 
+def batch_subset(sizes):
+    """The seeded 16-system subset the CPU baseline also times, plus the
+    smallest and the largest system."""
+    pick = set(np.random.default_rng(2112).choice(256, 16, replace=False).tolist())
+    return sorted(pick | {int(sizes.argmin()), int(sizes.argmax())})
+
+
 def test_full_batch_against_separate_solves_and_oracle():
     # the 256 uneven diffusion systems (edges U[16,64]) x 4 right-hand sides
     need_gpu()
@@ -150,20 +154,88 @@ def test_full_batch_against_separate_solves_and_oracle():
     hs = [make(s, 1, 1) for s in systems]
     st, sw, rr = b.jac_solve_batched(hs, 1e-8, 100000)
     assert st == b.JAC_OK
-    sizes = np.array([s.n for s in systems])
-    rng = np.random.default_rng(2112)
-    pick = sorted({int(sizes.argmin()), int(sizes.argmax())} | set(rng.choice(256, 6, replace=False).tolist()))
-    xb = {si: get_x(hs[si], systems[si].n, 4) for si in pick}
+    xb = [get_x(h, s.n, 4) for h, s in zip(hs, systems)]
     for h in hs:
         b.jac_destroy(h)
-    for si in pick:
-        s = systems[si]
+    # every column: bit-identical to its system solved alone, and its FP64
+    # residual (recomputed here) passes the test it stopped on
+    for si, s in enumerate(systems):
         h = make(s, 1, 1)
         st1, sw1, rr1 = b.jac_solve(h, 1e-8, 100000)
         x1 = get_x(h, s.n, 4)
         b.jac_destroy(h)
-        assert np.array_equal(sw[si], sw1) and np.array_equal(xb[si], x1), si
+        assert np.array_equal(sw[si, :4], sw1) and np.array_equal(xb[si], x1), si
+        A = s.scipy()
         for c in range(4):
-            sto, xo, ko, rro = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[c], 1e-8, 100000, threads=16)
-            assert sto == ref.OK and sw[si, c] == ko, (si, c)
-            assert rel_inf(xb[si][c], xo) <= 1e-10, (si, c)
+            res = np.linalg.norm(s.b[c] - A @ xb[si][c]) / np.linalg.norm(s.b[c])
+            assert res <= 1e-8 * (1 + 1e-6) and abs(res - rr[si, c]) <= 1e-6 * res, (si, c)
+    # a seeded subset against the oracle, column by column
+    sizes = np.array([s.n for s in systems])
+    jobs = [(si, c) for si in batch_subset(sizes) for c in range(4)]
+
+    def oracle(job):
+        si, c = job
+        s = systems[si]
+        return ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[c], 1e-8, 100000)
+
+    with ThreadPoolExecutor(16) as ex:
+        out = list(ex.map(oracle, jobs))
+    for (si, c), (sto, xo, ko, rro) in zip(jobs, out):
+        assert sto == ref.OK and sw[si, c] == ko, (si, c)
+        assert rel_inf(xb[si][c], xo) <= 1e-10, (si, c)
+
+
+@pytest.mark.parametrize("mode,sub", [(1, None), (2, None), (3, (8, 8, 8)), (3, (4, 4, 4))])
+def test_split_arrays_bit_exact_at_full_size(big, mode, sub):
+    # 128^3, 64 parts: order, bounds, receive lists and send lists of the
+    # library's split equal the oracle partitioner's, array for array
+    need_gpu()
+    b = B()
+    s = big
+    h = make(s, mode, 64, sub)
+    got = b.jac_get_partition(h)
+    sl = b.jac_get_send_lists(h)
+    b.jac_destroy(h)
+    exp = OP.partition(s.row_ptr, s.col_idx, mode, 64, grid=(128, 128, 128), sub_grid=sub)
+    for key in ("perm", "bounds", "recv_ptr", "recv_idx"):
+        assert np.array_equal(got[key], exp[key]), key
+    sptr, sdest, sidx = OP.send_lists(exp["recv_ptr"], exp["recv_idx"], exp["owner"], 64)
+    assert np.array_equal(sl["send_ptr"], sptr)
+    assert np.array_equal(sl["send_dest"], sdest) and np.array_equal(sl["send_idx"], sidx)
+    halo = {1: 0, 2: 2064384, 3: 458752 if sub == (8, 8, 8) else 294912}[mode]
+    assert len(got["recv_idx"]) == halo
+
+
+def test_adjoint_at_full_size_against_full_storage_oracle():
+    """The differentiation workload at its full size: 64^3 diffusion, K = 400
+    sweeps, reverse segments of 20.  dL/db and dL/dvals from jac_adjoint
+    against the oracle's full-storage reverse sweep, element by element, and
+    dL/dtheta from the autograd Function against the oracle's chain rule."""
+    need_gpu()
+    from paper_2112_02377_amd.autograd import JacobiK, diffusion_values
+    b = B()
+    s = W.diffusion_adjoint(64)
+    K, c = 400, 20
+    t = s.extra["x_target"]
+    st, xo, _ = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K, threads=16)
+    g = xo - t
+    sto, gbo, gvo, xk = ref.adjoint(s.row_ptr, s.col_idx, s.vals, s.b[0], K, g)
+    assert sto == ref.OK
+    h = make(s, 1, 1)
+    gb = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    gv = torch.empty(s.nnz, dtype=torch.float64, device="cuda")
+    b.jac_adjoint(h, K, c, torch.from_numpy(g).cuda(), gb, gv)
+    torch.cuda.synchronize()
+    gb, gv = gb.cpu().numpy(), gv.cpu().numpy()
+    assert np.abs(gb - gbo).max() <= 1e-10 * np.abs(gbo).max()
+    assert np.abs(gv - gvo).max() <= 1e-10 * np.abs(gvo).max()
+    assert rel_inf(get_x(h, s.n)[0], xk) <= 1e-12
+    # through torch: theta -> values -> K sweeps -> loss
+    theta = torch.from_numpy(s.extra["theta"]).cuda().requires_grad_(True)
+    vals = diffusion_values(theta, s.grid, s.row_ptr, s.extra["slot"])
+    x = JacobiK.apply(vals, torch.from_numpy(s.b[0]).cuda(), h, K, c)
+    (0.5 * ((x - torch.from_numpy(t).cuda()) ** 2).sum()).backward()
+    gth = theta.grad.cpu().numpy()
+    gth_o = ref.theta_grad(s.extra["theta"], s.grid, s.row_ptr, s.extra["slot"], gvo)
+    assert np.abs(gth - gth_o).max() <= 1e-10 * np.abs(gth_o).max()
+    b.jac_destroy(h)

@@ -73,3 +73,60 @@ def test_refine_stops_soft_when_inner_budget_is_exhausted():
     x = get_x(h, s.n)[0]
     assert abs(fp64_relres(s, x) - rr[0]) <= 1e-6 * rr[0]
     b.jac_destroy(h)
+
+
+def test_refine_keeps_going_on_a_slowly_converging_laplacian():
+    # 64^3 7-point Laplacian to 1e-8: 256 inner sweeps cut the residual by
+    # only about 0.5-0.6 per outer step, which is progress, not stagnation
+    # (the FP64 ratio follows the inner one); the result is checked against
+    # the FP64 oracle's solution and sweep count
+    need_gpu()
+    b = B()
+    s = W.laplace7(64, workload=1)
+    h = make(s, 2, 16)
+    st, sw, rr = b.jac_solve(h, 1e-8, 1000000, b.JAC_NORM_L2_REL, b.JAC_FP32_REFINE)
+    x = get_x(h, s.n)[0]
+    b.jac_destroy(h)
+    assert st == b.JAC_OK
+    assert fp64_relres(s, x) <= 1e-8 * 1.001
+    sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-8, 1000000, threads=16)
+    assert sto == ref.OK
+    # both residuals are below 1e-8 ||b||: ||x - xo|| <= 2e-8 ||b|| / lambda_min
+    lam = 6 * (1 - np.cos(np.pi / 65))
+    assert np.linalg.norm(x - xo) <= 2e-8 * np.linalg.norm(s.b[0]) / lam
+    assert ko <= sw[0] <= 1.25 * ko + 10, (sw[0], ko)
+
+
+def test_tuned_refinement_meets_the_fp64_bars_at_full_size(tmp_path, monkeypatch):
+    # the 96^3 27-point system of the refinement comparison, with the tile
+    # shape and the inner stop parameters picked by jac_autotune
+    need_gpu()
+    b = B()
+    monkeypatch.setenv("JAC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    s = W.fe27(96, workload=3)
+    h = make(s, 1, 64)
+    b.jac_autotune(h, 20)
+    tau = b.jac_get_option(h, b.JAC_OPT_INNER_TOL) * 1e-9
+    mmax = b.jac_get_option(h, b.JAC_OPT_INNER_MAX)
+    print(f"tuned inner tolerance {tau:g}, inner sweep cap {mmax}")
+    st, sw, rr = b.jac_solve(h, 1e-10, 100000, b.JAC_NORM_L2_REL, b.JAC_FP32_REFINE)
+    x = get_x(h, s.n)[0]
+    b.jac_destroy(h)
+    assert st == b.JAC_OK
+    assert fp64_relres(s, x) <= 1e-10 * 1.001
+    sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-10, 100000, threads=16)
+    assert sto == ref.OK
+    # error bar from the arithmetic: x and xo solve A y = b up to their
+    # residuals, so ||x - xo||_2 <= ||A^-1||_2 (||r|| + ||r_o||), and for this
+    # symmetric diagonally dominant matrix 1/||A^-1||_2 = lambda_min is at
+    # least the smallest Gershgorin margin a_ii - sum_j |a_ij|
+    A = s.scipy()
+    d = A.diagonal()
+    off = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(d)
+    margin = float((d - off).min())
+    assert margin > 0
+    r = np.linalg.norm(s.b[0] - A @ x)
+    ro = np.linalg.norm(s.b[0] - A @ xo)
+    err = np.linalg.norm(x - xo)
+    assert err <= (r + ro) / margin, (err, r, ro, margin)
+    print(f"max |x - x_oracle| / max |x_oracle| = {np.abs(x - xo).max() / np.abs(xo).max():.3e}")

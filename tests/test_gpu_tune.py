@@ -29,7 +29,12 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
              (512, 128), (512, 512), (1024, 512), (2048, 512), (4096, 512)}
     assert (rows, block) in cands
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].split("|")[1].split()[:2] == [str(rows), str(block)]
+    assert len(lines) == 2 and lines[0].split("|")[1].split()[:2] == [str(rows), str(block)]
+    # the refinement's inner stop parameters: one of the candidate pairs
+    tau = b.jac_get_option(h, b.JAC_OPT_INNER_TOL)
+    mmax = b.jac_get_option(h, b.JAC_OPT_INNER_MAX)
+    assert tau in (1000000, 100000, 10000, 1000) and mmax in (64, 256, 1024, 4096)
+    assert lines[1].startswith("refine ") and lines[1].split("|")[1].split()[:2] == [str(tau), str(mmax)]
     set_x(h, np.zeros(s.n))
     st, sw, rr = b.jac_solve(h, 1e-8, 10000)
     sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-8, 10000)
@@ -39,7 +44,8 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     h2 = make(s, 2, 4)
     b.jac_autotune(h2, 5)
     assert b.jac_get_option(h2, b.JAC_OPT_TILE_ROWS) == rows and b.jac_get_option(h2, b.JAC_OPT_BLOCK) == block
-    assert len(cache.read_text().splitlines()) == 1
+    assert b.jac_get_option(h2, b.JAC_OPT_INNER_TOL) == tau and b.jac_get_option(h2, b.JAC_OPT_INNER_MAX) == mmax
+    assert len(cache.read_text().splitlines()) == 2
     b.jac_destroy(h2)
 
 
