@@ -248,6 +248,24 @@ jac_status jac_get_x(jac_handle h, double *x_dev);
  * the iterate each sweep starts from). */
 jac_status jac_sweep(jac_handle h, int32_t nsweeps, double *hist_dev);
 
+/* jac_sweep without allocation, for callers that cannot allocate device
+ * memory during the call (code captured into a HIP graph, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * kernels as jac_sweep, bit for bit: nsweeps synchronous sweeps from the
+ * current x, with ||b - A x_k||_2 of every sweep in hist_dev when it is not
+ * NULL.  The call's scratch (the system descriptor, the loop state and the
+ * per-tile norm partials) lives in a static 1 MiB device array that the
+ * library holds on each device it runs on until the process ends; the
+ * handle's own buffers (matrix, b, iterates) were allocated when it was
+ * created and split.  The partials need 16 * ntiles * nrhs bytes of the
+ * array's 1 MiB - 1 KiB (jac_info.ntiles): a split with more tiles gives
+ * JAC_E_INVALID (use larger tiles, JAC_OPT_TILE_ROWS, or jac_sweep).  Always
+ * one launch per sweep (JAC_OPT_LOOP is ignored) and never timed
+ * (JAC_OPT_TIMING is ignored).  Every call on a device shares that device's
+ * array: calls that overlap on one device (on different streams or threads)
+ * race and must not be issued. */
+jac_status jac_sweep_noalloc(jac_handle h, int32_t nsweeps, double *hist_dev);
+
 /* Solve from the current x with the vectorial algorithm's test (section 3):
  * for k = 0, 1, ...: evaluate r_k; stop with x_k when its norm passes
  * (norm <= tol); at k == maxit return x_maxit and JAC_NOT_CONVERGED.  Each

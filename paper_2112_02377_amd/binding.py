@@ -33,7 +33,7 @@ EXPORTS = ["jac_create", "jac_set_values", "jac_set_rhs", "jac_set_grid", "jac_p
            "jac_set_x", "jac_get_x", "jac_sweep", "jac_solve", "jac_solve_batched", "jac_adjoint", "jac_autotune",
            "jac_set_option", "jac_get_option", "jac_get_info", "jac_destroy", "jac_status_string", "jac_last_error",
            "jac_graph_partition", "jac_solve_async", "jac_get_send_lists", "jac_autotune_batched",
-           "jac_sweep_checkpointed"]
+           "jac_sweep_checkpointed", "jac_sweep_noalloc"]
 
 
 class jac_info(C.Structure):
@@ -92,6 +92,7 @@ def lib():
             "jac_get_send_lists": [_vp, _i32p, _i32p, _i32p, _i64p],
             "jac_autotune_batched": [C.POINTER(_vp), C.c_int32, C.c_int32],
             "jac_sweep_checkpointed": [_vp, C.c_int32, C.c_int32],
+            "jac_sweep_noalloc": [_vp, C.c_int32, _vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -221,6 +222,10 @@ def jac_get_x(h, x_dev):
 
 def jac_sweep(h, nsweeps, hist_dev=None):
     return _check(lib().jac_sweep(h, int(nsweeps), _dev(hist_dev)))
+
+
+def jac_sweep_noalloc(h, nsweeps, hist_dev=None):
+    return _check(lib().jac_sweep_noalloc(h, int(nsweeps), _dev(hist_dev)))
 
 
 def jac_solve(h, tol, maxit, norm=JAC_NORM_L2_REL, prec=JAC_FP64, nrhs=None):
