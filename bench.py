@@ -60,6 +60,9 @@ def parse():
                     help="skip the batched solve in one persistent (cooperative) launch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
+    ap.add_argument("--batched-probe", type=int, default=0,
+                    help="only run this many lockstep sweeps of the 256-system, 4-column batch (counter "
+                         "runs of the batched kernel) and exit")
     return ap.parse_args()
 
 
@@ -686,6 +689,20 @@ def main():
         return
     from paper_2112_02377_amd import binding as B
     from paper_2112_02377_amd import workloads as W
+
+    if args.batched_probe:
+        systems = W.diffusion_batch(256, workload=4)
+        hs = [B.jac_create(x.n, x.row_ptr, x.col_idx, x.vals, 4, x.b.reshape(-1)) for x in systems]
+        # tolerance 0: every column runs the given sweeps (plus the last test)
+        B.jac_solve_batched(hs, 0.0, args.batched_probe)
+        torch.cuda.synchronize()
+        for h in hs:
+            B.jac_destroy(h)
+        print(json.dumps({"batched_probe_sweeps": args.batched_probe, "systems": len(systems),
+                          "rows": sum(x.n for x in systems),
+                          "lean_bytes_per_full_sweep": sum(W.lean_bytes_per_sweep(x.n, x.nnz, 4) for x in systems)}),
+              flush=True)
+        return
 
     N, K = args.N, args.sweeps
     s = W.laplace7(N, workload=2)

@@ -86,7 +86,8 @@ typedef enum {
                                 LDS per workgroup (160 KiB on gfx950)          */
     JAC_OPT_LOOP = 4,        /* 0 = one launch per sweep (default), 1 = persistent
                                 cooperative loop with a grid barrier per sweep     */
-    JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU (0 = occupancy)  */
+    JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU, default 2 (0 =
+                                as many as fit: 5 for the FP64 kernels)         */
     JAC_OPT_INNER_TOL = 6,   /* FP32 refinement: inner relative residual, x1e-9     */
     JAC_OPT_INNER_MAX = 7,   /* FP32 refinement: max inner sweeps per outer step    */
     JAC_OPT_CKPT_MEM_MB = 8, /* adjoint: cap on its device buffers (MiB), default

@@ -33,7 +33,7 @@ struct Options {
     int32_t block = 256;
     int32_t lds_elems = 4096;
     int32_t loop = 0;          // 0 one launch per sweep, 1 persistent cooperative loop
-    int32_t wg_per_cu = 0;
+    int32_t wg_per_cu = 2;     // persistent loop: measured best at 128^3 and on the 256-system batch
     double inner_tol = 1e-5;
     int32_t inner_max = 256;
     int64_t ckpt_mb = 4096;

@@ -6,6 +6,10 @@
 // usage: host_plan_check N mode nparts [sub [layout]]   (mode 1 JB, 2 JBO, 3 JSS;
 // layout: 0 the planner's choice, 1 no shift tables, 2 no shift tables and
 // global 32-bit columns for the unstaged split)
+//    or: host_plan_check --csr FILE mode nparts partitioner
+// (FILE: int32 n, int64 nnz, int32 row_ptr[n+1], int32 col_idx[nnz], 0-based,
+// columns ascending; without a grid, substructuring takes nparts contiguous
+// subdomains)
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -30,12 +34,29 @@ static int bad(const char* what, long long a, long long b)
 int main(int argc, char** argv)
 {
     if (argc < 4) return 2;
-    const int N = atoi(argv[1]), mode = atoi(argv[2]), P = atoi(argv[3]);
-    const int sg = argc > 4 ? atoi(argv[4]) : 2;
-    const int layout = argc > 5 ? atoi(argv[5]) : 0;
+    const bool from_file = std::string(argv[1]) == "--csr";
+    const int N = from_file ? 0 : atoi(argv[1]);
+    const int mode = atoi(argv[2 + from_file]), P = atoi(argv[3 + from_file]);
+    const int sg = !from_file && argc > 4 ? atoi(argv[4]) : 2;
+    const int layout = !from_file && argc > 5 ? atoi(argv[5]) : 0;
+    const int partitioner = from_file && argc > 5 ? atoi(argv[5]) : 0;
     Csr a;
-    a.n = N * N * N;
-    a.rp.push_back(0);
+    if (from_file) {
+        FILE* f = fopen(argv[2], "rb");
+        if (!f) return bad("open", 0, 0);
+        int64_t nnz = 0;
+        bool ok = fread(&a.n, 4, 1, f) == 1 && fread(&nnz, 8, 1, f) == 1;
+        a.rp.resize((size_t)a.n + 1);
+        a.ci.resize((size_t)nnz);
+        ok = ok && fread(a.rp.data(), 4, a.rp.size(), f) == a.rp.size() && fread(a.ci.data(), 4, a.ci.size(), f) == a.ci.size();
+        fclose(f);
+        if (!ok) return bad("read", 0, 0);
+        a.v.assign(a.ci.size(), -1.0);
+    }
+    else {
+        a.n = N * N * N;
+        a.rp.push_back(0);
+    }
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
             for (int x = 0; x < N; ++x) {
@@ -51,7 +72,8 @@ int main(int argc, char** argv)
             }
     const int32_t grid[3] = {N, N, N}, sub[3] = {sg, sg, sg};
     try {
-        Partition part = make_partition(a, mode, P, mode == JAC_SUBSTRUCT ? sub : nullptr, grid, 0);
+        Partition part = make_partition(a, mode, P, mode == JAC_SUBSTRUCT && !from_file ? sub : nullptr,
+                                        from_file ? nullptr : grid, partitioner);
         std::vector<int64_t> src;
         Csr pa = permute(a, part.perm, part.iperm, &src);
         PlanParams prm;

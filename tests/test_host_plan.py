@@ -73,3 +73,36 @@ def test_tile_cost_spread_and_xcd_ranges(checker):
     assert jss["spread"] > 1.25
     counts = [v - u for u, v in zip(jss["xcd"], jss["xcd"][1:])]
     assert sum(counts) == jss["ntiles"] and min(counts) > 0
+
+
+def random_csr(path, seed, n=3000):
+    """A seeded random pattern with the diagonal, short local rows and some
+    rows of 50-300 entries spread over all columns (wider than a 64-lane slot
+    mask), written for the checker's --csr mode."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        if rng.random() < 0.05:
+            c = rng.integers(0, n, int(rng.integers(50, 300)))
+        else:
+            c = i + rng.integers(-30, 31, int(rng.integers(0, 8)))
+        c = np.unique(np.concatenate([c[(c >= 0) & (c < n)], [i]]))
+        rows.append(c.astype(np.int32))
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    with open(path, "wb") as f:
+        f.write(np.array([n], np.int32).tobytes() + np.array([rp[-1]], np.int64).tobytes())
+        f.write(rp.tobytes() + np.concatenate(rows).tobytes())
+
+
+@pytest.mark.parametrize("mode,P,part", [(1, 3, 0), (2, 4, 0), (2, 5, 1), (3, 6, 0), (3, 4, 1)])
+def test_random_patterns_with_rows_wider_than_a_slot_mask(checker, tmp_path, mode, P, part):
+    # rows of hundreds of entries make slices wider than 64 slots (as wide as
+    # the widest row): the split and every layout must plan and decode them
+    path = str(tmp_path / "a.bin")
+    random_csr(path, 17 + mode)
+    p = subprocess.run([checker, "--csr", path, str(mode), str(P), str(part)], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert int(p.stdout.split()[1]) in (0, 1, 2, 3, 4)
