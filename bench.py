@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--hbm-sweeps", type=int, default=200, help="sweeps per timed loop of the HBM-bound control")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the batched solve in one persistent (cooperative) launch")
+    ap.add_argument("--secondary-legs", default="refine,batched,adjoint,set1,partitions,async,controls",
+                    help="comma-separated secondary comparisons to run")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     ap.add_argument("--batched-probe", type=int, default=0,
@@ -211,7 +213,10 @@ def _timed(torch, stream, fn):
     return e0.elapsed_time(e1), r
 
 
-def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
+SECONDARY_LEGS = ("refine", "batched", "adjoint", "set1", "partitions", "async", "controls")
+
+
+def secondary(B, W, torch, stream, with_oracle=True, persistent=True, legs=SECONDARY_LEGS):
     """The comparisons the metric names, each against the plain FP64 sweep on
     the same GPU: FP32 inner sweeps with FP64 refinement (96^3 27-point
     FE-like matrix, to 1e-10), the batched persistent solve (256 diffusion
@@ -221,13 +226,43 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
     with its stop test, beside its iteration counts and CPU-cluster times, the
     weighted partitioners against equal-row bands, the asynchronous
     relaxation against the synchronous solve, and the control configurations
-    (20^3 solves, 128^3 with 4x4x4 subdomains, 192^3).
+    (20^3 solves, 128^3 with 4x4x4 subdomains).  `legs` selects among them.
     Times are HIP-event times on the handles' stream."""
-    import numpy as np
     out = {}
+    if "refine" in legs:
+        log("secondary: FP32 refinement")
+        out["fp32_refine"] = refine_leg(B, W, torch, stream, with_oracle)
+    if "batched" in legs:
+        log("secondary: batched")
+        out["batched"] = batched_leg(B, W, torch, stream, persistent)
+    if "adjoint" in legs:
+        log("secondary: adjoint")
+        out["adjoint"] = adjoint_leg(B, W, torch, stream)
+    if "set1" in legs:
+        # the paper's Set-1 cubes (Q1 FE stand-ins) with its stop test
+        log("secondary: Set-1 cubes")
+        out["paper_set1"] = set1(B, W, torch, stream)
+    if "partitions" in legs:
+        # weighted partitions against equal-row bands
+        log("secondary: partitioners")
+        out["partitions"] = partitions(B, W, torch, stream)
+    if "async" in legs:
+        # asynchronous relaxation against the synchronous solve
+        log("secondary: asynchronous")
+        out["async"] = async_vs_sync(B, W, torch, stream)
+    if "controls" in legs:
+        # the small configuration's solves and the 128^3 substructuring control
+        log("secondary: controls")
+        out["controls"] = controls(B, W, torch, stream)
+    return out
+
+
+def refine_leg(B, W, torch, stream, with_oracle):
+    """FP32 inner sweeps under FP64 refinement against the FP64 solve, on the
+    96^3 27-point FE-like matrix to relative 1e-10: default inner stop
+    parameters, then the autotuner's tile shape and parameters."""
+    import numpy as np
     sc = stream.cuda_stream
-    log("secondary: FP32 refinement")
-    # -- FP32 refinement
     s = W.fe27(96, workload=3)
     h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
     B.jac_partition(h, B.JAC_BANDROW, 64)
@@ -245,6 +280,7 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
     # the autotuner's tile shape and inner stop parameters (tuning not timed)
     B.jac_autotune(h, 20)
     tuned = {"tile_rows": B.jac_get_option(h, B.JAC_OPT_TILE_ROWS), "block": B.jac_get_option(h, B.JAC_OPT_BLOCK),
+             "grid": B.jac_get_option(h, B.JAC_OPT_GRID),
              "inner_tol": B.jac_get_option(h, B.JAC_OPT_INNER_TOL) * 1e-9,
              "inner_max": B.jac_get_option(h, B.JAC_OPT_INNER_MAX)}
     for prec, name in ((B.JAC_FP64, "fp64_tuned"), (B.JAC_FP32_REFINE, "fp32_refine_tuned")):
@@ -266,7 +302,7 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
         scale = float(abs(xo).max())
         ref_err = {k: float(abs(v["x"] - xo).max() / scale) for k, v in res.items()}
         ref_err["oracle_sweeps"] = int(ko)
-    out["fp32_refine"] = {
+    out = {
         "workload": f"fe27 96^3 (n={s.n}, nnz={s.nnz}), 1.05-dominant, tol 1e-10, 64 bands",
         "fp64_matrix_loads": "kept" if info["keep_matrix"] else "streamed",
         "fp64_ms": res["fp64"]["ms"], "fp64_sweeps": res["fp64"]["sweeps"], "fp64_relres": res["fp64"]["relres"],
@@ -283,8 +319,15 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
         "byte_model": "FP64 sweep: lean (12 nnz + 4 (n+1) + 24 n); FP32 inner sweep: 8 nnz + 4 (n+1) + 16 n",
         "max_rel_err_vs_fp64_oracle": ref_err}
     B.jac_destroy(h)
-    # -- batched
-    log("secondary: batched")
+    return out
+
+
+def batched_leg(B, W, torch, stream, persistent):
+    """256 diffusion systems x 4 right-hand sides to relative 1e-8: batched
+    (per-sweep launches, default and tuned tiles; one persistent launch)
+    against 256 separate solves, and the seeded 16-system subset."""
+    import numpy as np
+    sc = stream.cuda_stream
     systems = W.diffusion_batch(256, workload=4)
     hs = [B.jac_create(x.n, x.row_ptr, x.col_idx, x.vals, 4, x.b.reshape(-1), stream=sc) for x in systems]
     # 256 separate solves and the batched solve, both on the default tile
@@ -321,7 +364,7 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
     alg = 0
     for x, k in zip(systems, swb):
         alg += W.lean_bytes_per_sweep(x.n, x.nnz, 4) * (int(k[:4].max()) + 1)
-    out["batched"] = {
+    out = {
         "workload": f"256 diffusion systems, edges U[16,64], n total {sum(x.n for x in systems)}, 4 rhs, tol 1e-8",
         "batched_ms": round(ms_b, 3), "persistent_ms": None if ms_p is None else round(ms_p, 3),
         "sequential_ms": round(ms_s, 3), "batched_default_tiles_ms": round(ms_d, 3),
@@ -340,8 +383,14 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
                 "jac_autotune_batched picked for the batch"}
     for hh in hs:
         B.jac_destroy(hh)
-    # -- adjoint
-    log("secondary: adjoint")
+    return out
+
+
+def adjoint_leg(B, W, torch, stream):
+    """The adjoint of 400 sweeps at 64^3 (checkpoint every 20) against its
+    forward sweeps: all iterates stored, checkpoints reused from the
+    forward, and checkpoints every 20 with recomputed segments."""
+    sc = stream.cuda_stream
     s = W.diffusion_adjoint(64, workload=5)
     h = B.jac_create(s.n, s.row_ptr, s.col_idx, s.vals, 1, s.b.reshape(-1), stream=sc)
     gx = torch.from_numpy(s.extra["x_target"]).cuda()
@@ -367,7 +416,7 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
     B.jac_adjoint(h, 400, 20, gx, gb, gv)
     B.jac_set_x(h, None)
     ms_rc, _ = _timed(torch, stream, lambda: B.jac_adjoint(h, 400, 20, gx, gb, gv))
-    out["adjoint"] = {"workload": "diffusion 64^3, K = 400 sweeps, reverse segments of 20; all 401 iterates "
+    out = {"workload": "diffusion 64^3, K = 400 sweeps, reverse segments of 20; all 401 iterates "
                                   "stored (841 MB, within the default 4 GiB cap)", "forward_ms": round(ms_f, 3),
                       "adjoint_ms": round(ms_a, 3), "adjoint_over_forward": round(ms_a / ms_f, 3),
                       "forward_checkpointed_ms": round(ms_fc, 3), "reverse_reusing_checkpoints_ms": round(ms_r, 3),
@@ -376,16 +425,6 @@ def secondary(B, W, torch, stream, with_oracle=True, persistent=True):
                       "adjoint_checkpoint_every_20_over_forward": round(ms_rc / ms_f, 3),
                       "forward_GBps": round(400 * fb / ms_f / 1e6, 1)}
     B.jac_destroy(h)
-    # -- the paper's Set-1 cubes (Q1 FE stand-ins) with its stop test
-    log("secondary: Set-1 cubes")
-    out["paper_set1"] = set1(B, W, torch, stream)
-    log("secondary: partitioners, asynchronous, controls")
-    # -- weighted partitions against equal-row bands
-    out["partitions"] = partitions(B, W, torch, stream)
-    # -- asynchronous relaxation against the synchronous solve
-    out["async"] = async_vs_sync(B, W, torch, stream)
-    # -- the small configuration's solves and the 128^3 / 192^3 controls
-    out["controls"] = controls(B, W, torch, stream)
     return out
 
 
@@ -528,6 +567,7 @@ def set1(B, W, torch, stream):
             # default tile shape, then the autotuner's pick (tuning not timed)
             B.jac_set_option(h, B.JAC_OPT_TILE_ROWS, 512)
             B.jac_set_option(h, B.JAC_OPT_BLOCK, 256)
+            B.jac_set_option(h, B.JAC_OPT_GRID, 0)
             B.jac_partition(h, mode, 64, sg)
             for tuned in (False, True):
                 if tuned:
@@ -540,7 +580,7 @@ def set1(B, W, torch, stream):
                 e = {"iters": int(sw[0]) + 1, "ms": round(ms, 3), "final_res_inf": float(rr[0]),
                      "GBps": round((int(sw[0]) + 1) * W.lean_bytes_per_sweep(s.n, s.nnz) / ms / 1e6, 1),
                      "tile_rows": B.jac_get_option(h, B.JAC_OPT_TILE_ROWS),
-                     "block": B.jac_get_option(h, B.JAC_OPT_BLOCK)}
+                     "block": B.jac_get_option(h, B.JAC_OPT_BLOCK), "grid": B.jac_get_option(h, B.JAC_OPT_GRID)}
                 if tuned:
                     r[name]["tuned"] = e
                 else:
@@ -749,8 +789,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, sub16)
         log("CPU oracle baseline done")
     if not args.no_secondary:
+        legs = [x for x in args.secondary_legs.split(",") if x]
+        bad = [x for x in legs if x not in SECONDARY_LEGS]
+        if bad:
+            print(f"unknown secondary legs {bad}; known: {','.join(SECONDARY_LEGS)}", file=sys.stderr)
+            sys.exit(2)
         out["secondary"] = secondary(B, W, torch, stream, with_oracle=not args.no_cpu,
-                                     persistent=not args.no_persistent)
+                                     persistent=not args.no_persistent, legs=legs)
     print(json.dumps(out), flush=True)
 
 

@@ -334,8 +334,13 @@ jac_status jac_sweep_checkpointed(jac_handle h, int32_t K, int32_t ckpt_every);
 jac_status jac_adjoint(jac_handle h, int32_t K, int32_t ckpt_every, const double *gx_dev, double *gb_dev,
                        double *gvals_dev);
 
-/* Time candidate tile shapes and loop settings on this handle and keep the
- * fastest (x is restored afterwards).  The choice is cached on disk under
+/* Time candidate tile shapes (rows per tile, threads per workgroup) on this
+ * handle and keep the fastest, with the launch grid of per-sweep launches
+ * (a workgroup per tile or one resident round) when JAC_OPT_GRID is left
+ * automatic; then time FP32 refinements from x = 0 to relative 1e-10 for
+ * candidate inner stop parameters (JAC_OPT_INNER_TOL in {1e-3, 1e-4, 1e-5,
+ * 1e-6}, JAC_OPT_INNER_MAX in {64, 256, 1024, 4096}) and keep the quickest.
+ * x is restored afterwards.  The choices are cached on disk under
  * $JAC_TUNE_CACHE (if set), keyed by the matrix shape and split. */
 jac_status jac_autotune(jac_handle h, int32_t sweeps_per_trial);
 

@@ -118,3 +118,31 @@ def test_rejected_arguments():
     st, sw, rr = b.jac_solve(h, 1e-12, 10)
     assert st == b.JAC_OK and np.array_equal(get_x(h, 2)[0], np.array([0.5, 0.5]))
     b.jac_destroy(h)
+
+
+@pytest.mark.parametrize("mode,sub", [(2, None), (3, (2, 2, 2))])
+def test_lds_budget_bounds_staged_footprints_for_four_columns(mode, sub):
+    # 16384 staged entries of 4 doubles would need 512 KiB of LDS per
+    # workgroup: the split bounds each tile's footprint by the device's LDS
+    # (160 KiB on gfx950), splitting tiles or sweeping unstaged, and the
+    # sweeps equal the default budget's to rounding and the oracle's
+    need_gpu()
+    b = B()
+    s = W.laplace7(24, workload=1)
+    rng = np.random.default_rng(11)
+    s = W.CSRSystem(s.row_ptr, s.col_idx, s.vals, np.vstack([s.b[0]] + [rng.uniform(-1, 1, s.n) for _ in range(3)]),
+                    grid=s.grid)
+    K = 9
+    out = []
+    for opts in ({}, {b.JAC_OPT_LDS_ELEMS: 16384, b.JAC_OPT_TILE_ROWS: 8192, b.JAC_OPT_BLOCK: 512}):
+        h = make(s, mode, 2, sub, opts=opts)         # parts of 6912 rows: one tile would stage ~8000 entries
+        info = b.jac_get_info(h)
+        assert info["max_footprint"] * 4 * 8 <= 160 * 1024, info["max_footprint"]
+        hist = sweep(h, K, 4)
+        out.append((hist, get_x(h, s.n, 4)))
+        b.jac_destroy(h)
+    for c in range(4):
+        _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[c], K)
+        for hist, x in out:
+            assert rel_inf(x[c], xr) <= 1e-12, c
+            assert np.all(np.abs(hist[:, c] - hr) <= 1e-12 * hr), c

@@ -29,12 +29,15 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
              (512, 128), (512, 512), (1024, 512), (2048, 512), (4096, 512)}
     assert (rows, block) in cands
     lines = cache.read_text().splitlines()
-    assert len(lines) == 2 and lines[0].split("|")[1].split()[:2] == [str(rows), str(block)]
+    assert len(lines) == 3 and lines[0].split("|")[1].split()[:2] == [str(rows), str(block)]
+    # the launch grid, tuned since it was left automatic
+    grid = b.jac_get_option(h, b.JAC_OPT_GRID)
+    assert grid in (1, 2) and lines[1].startswith("grid ") and lines[1].split("|")[1].split()[0] == str(grid)
     # the refinement's inner stop parameters: one of the candidate pairs
     tau = b.jac_get_option(h, b.JAC_OPT_INNER_TOL)
     mmax = b.jac_get_option(h, b.JAC_OPT_INNER_MAX)
     assert tau in (1000000, 100000, 10000, 1000) and mmax in (64, 256, 1024, 4096)
-    assert lines[1].startswith("refine ") and lines[1].split("|")[1].split()[:2] == [str(tau), str(mmax)]
+    assert lines[2].startswith("refine ") and lines[2].split("|")[1].split()[:2] == [str(tau), str(mmax)]
     set_x(h, np.zeros(s.n))
     st, sw, rr = b.jac_solve(h, 1e-8, 10000)
     sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-8, 10000)
@@ -45,7 +48,8 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     b.jac_autotune(h2, 5)
     assert b.jac_get_option(h2, b.JAC_OPT_TILE_ROWS) == rows and b.jac_get_option(h2, b.JAC_OPT_BLOCK) == block
     assert b.jac_get_option(h2, b.JAC_OPT_INNER_TOL) == tau and b.jac_get_option(h2, b.JAC_OPT_INNER_MAX) == mmax
-    assert len(cache.read_text().splitlines()) == 2
+    assert b.jac_get_option(h2, b.JAC_OPT_GRID) == grid
+    assert len(cache.read_text().splitlines()) == 3
     b.jac_destroy(h2)
 
 
