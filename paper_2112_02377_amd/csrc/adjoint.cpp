@@ -169,8 +169,8 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
         d.state.ensure(sizeof(SysState));
         JAC_HIP(hipStreamSynchronize(st));   // fs is a temporary
         void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
-        const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
-        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const int fpb = h.lds_fp_bytes(false), tab = h.lds_tab();
+        const size_t lds = loop_lds_bytes(fpb, tab, 0);
         const int grid = sweep_grid(h, fn, h.opt.block, lds);
         launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, CK(0), st);
         launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
@@ -183,7 +183,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
             p.k0 = 0;
             p.kend = 1;
             p.solve = 0;
-            launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, runs);
+            launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, tab);
         }
         JAC_HIP(hipMemcpyAsync(d.x0.p, CK(K), vec, hipMemcpyDeviceToDevice, st));
         h.ckpt_K = K;
@@ -199,8 +199,8 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
     double* xb[3] = {static_cast<double*>(d.x0.p), static_cast<double*>(d.x1.p), static_cast<double*>(d.x2.p)};
     auto CK = [&](int j) { return static_cast<double*>(d.adj_ck.p) + (size_t)j * n; };
     void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
-    const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
-    const size_t lds = loop_lds_bytes(fpb, runs, 0);
+    const int fpb = h.lds_fp_bytes(false), tab = h.lds_tab();
+    const size_t lds = loop_lds_bytes(fpb, tab, 0);
     const int grid = sweep_grid(h, fn, h.opt.block, lds);
     launch_gather_in(nullptr, static_cast<const int32_t*>(d.perm.p), n, 1, xb[0], st);
     launch_init_state(static_cast<SysState*>(d.state.p), 1, st);
@@ -213,7 +213,7 @@ static void forward_ckpt(Handle& h, int32_t K, int32_t c)
     p.solve = 0;
     for (int32_t k = 0; k < K; ++k) {
         if (k % c == 0) JAC_HIP(hipMemcpyAsync(CK(k / c), xb[k % 3], vec, hipMemcpyDeviceToDevice, st));
-        launch_sweep1(fn, grid, h.opt.block, lds, st, p, k, fpb, runs);
+        launch_sweep1(fn, grid, h.opt.block, lds, st, p, k, fpb, tab);
     }
     h.settle((uint32_t)(K % 3));
     h.ckpt_K = K;
@@ -329,8 +329,8 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         double* xK = static_cast<double*>(d.x0.p);
         // recompute sweeps: the kernel of the forward
         void* fn = sweep_kernel(false, 1, h.plan.colfmt, 0, sA.keep != 0);
-        const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
-        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const int fpb = h.lds_fp_bytes(false), tab = h.lds_tab();
+        const size_t lds = loop_lds_bytes(fpb, tab, 0);
         const int grid = sweep_grid(h, fn, h.opt.block, lds);
         if (K > 0) {
             // lambda_K (internal order), mu_K = D^{-1} lambda_K, gb = mu_K
@@ -360,7 +360,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
                     p.k0 = 0;
                     p.kend = 1;
                     p.solve = 0;
-                    launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, runs);
+                    launch_sweep1(fn, grid, h.opt.block, lds, st, p, 0, fpb, tab);
                 }
                 for (int32_t m = L - 1; m >= 0; --m) {
                     const int32_t k = k0 + m;

@@ -113,13 +113,14 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     Csr pa = permute(a, np.perm, np.iperm, &src);
     PlanParams prm;
     prm.tile_rows = opt.tile_rows;
-    // a staged tile's LDS holds its footprint (nrhs doubles per entry), two
-    // words per footprint run and the reduction scratch: bound the footprint
-    // so that the largest tile still fits one workgroup's LDS (a tile over
-    // the bound is split, down to single slices, or the plan goes unstaged)
+    // a staged tile's LDS holds its footprint (nrhs doubles per entry), its
+    // run lookup table (a word per footprint run, three per 64 entries) and
+    // the reduction scratch: bound the footprint so that the largest tile
+    // still fits one workgroup's LDS (a tile over the bound is split, down to
+    // single slices, or the plan goes unstaged)
     {
-        const int64_t avail = (int64_t)max_lds_bytes() - 8 * (int64_t)prm.max_runs - 1024;
-        const int64_t cap = std::max<int64_t>(avail / (8 * (int64_t)nrhs), kSlice);
+        const int64_t avail = (int64_t)max_lds_bytes() - 4 * (int64_t)prm.max_runs - 1024;
+        const int64_t cap = std::max<int64_t>(avail * kSlice / (64 * 8 * (int64_t)nrhs + 12) / kSlice * kSlice, kSlice);
         prm.lds_elems = (int32_t)std::min<int64_t>(opt.lds_elems, cap);
     }
     prm.staged = (mode != JAC_BANDROW);
@@ -148,19 +149,26 @@ void Handle::replan(int mode, int32_t nparts, const int32_t* sub_grid)
     if (plan.colfmt == COL_REL16) {
         upload(d.col16, plan.col16, stream);
         d.col32.reset();
-        d.tile_run0.reset(); d.run_start.reset(); d.run_lds.reset(); d.tile_fp.reset(); d.tile_own.reset();
+        d.tile_run0.reset(); d.run_lds.reset(); d.run_delta.reset();
+        d.tile_chunk0.reset(); d.chunk_bits.reset(); d.chunk_run.reset();
+        d.tile_fp.reset(); d.tile_own.reset();
     } else if (plan.prm.staged) {
         upload(d.col16, plan.col16, stream);
         d.col32.reset();
         upload(d.tile_run0, plan.tile_run0, stream);
-        upload(d.run_start, plan.run_start, stream);
         upload(d.run_lds, plan.run_lds, stream);
+        upload(d.run_delta, plan.run_delta, stream);
+        upload(d.tile_chunk0, plan.tile_chunk0, stream);
+        upload(d.chunk_bits, plan.chunk_bits, stream);
+        upload(d.chunk_run, plan.chunk_run, stream);
         upload(d.tile_fp, plan.tile_fp, stream);
         upload(d.tile_own, plan.tile_own, stream);
     } else {
         upload(d.col32, plan.col32, stream);
         d.col16.reset();
-        d.tile_run0.reset(); d.run_start.reset(); d.run_lds.reset(); d.tile_fp.reset(); d.tile_own.reset();
+        d.tile_run0.reset(); d.run_lds.reset(); d.run_delta.reset();
+        d.tile_chunk0.reset(); d.chunk_bits.reset(); d.chunk_run.reset();
+        d.tile_fp.reset(); d.tile_own.reset();
     }
     upload(d.shift, plan.shift, stream);
     upload(d.slot_of_caller, slot_of_caller, stream);
@@ -270,8 +278,11 @@ SysDev Handle::sysdev(bool fp32) const
     s.col32 = static_cast<const int32_t*>(d.col32.p);
     s.col16 = static_cast<const uint16_t*>(d.col16.p);
     s.tile_run0 = static_cast<const int32_t*>(d.tile_run0.p);
-    s.run_start = static_cast<const int32_t*>(d.run_start.p);
     s.run_lds = static_cast<const int32_t*>(d.run_lds.p);
+    s.run_delta = static_cast<const int32_t*>(d.run_delta.p);
+    s.tile_chunk0 = static_cast<const int32_t*>(d.tile_chunk0.p);
+    s.chunk_bits = static_cast<const uint64_t*>(d.chunk_bits.p);
+    s.chunk_run = static_cast<const int32_t*>(d.chunk_run.p);
     s.tile_fp = static_cast<const int32_t*>(d.tile_fp.p);
     s.tile_own = static_cast<const int32_t*>(d.tile_own.p);
     s.shift = static_cast<const int32_t*>(d.shift.p);
@@ -305,7 +316,7 @@ int Handle::lds_fp_bytes(bool fp32) const
     return (b + 15) / 16 * 16;
 }
 
-int Handle::lds_runs() const { return plan.prm.staged ? std::max(plan.max_runs, 1) : 0; }
+int Handle::lds_tab() const { return plan.prm.staged ? std::max(plan.max_tab, 2) : 0; }
 
 
 // Workgroups of a one-launch-per-sweep k_sweep of the handle's system, the
@@ -342,7 +353,7 @@ int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work)
 // Solve mode: stop tests up to kend = maxit.  States are initialised here.
 void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_t kend, int norm_inf, double* hist,
               DevMem& d_sys, DevMem& d_state, DevMem& d_tile_base, const std::vector<int32_t>& tile_base,
-              int fp_bytes, int runs, int colfmt, int nrhs, const std::vector<int64_t>* sys_bytes)
+              int fp_bytes, int tab, int colfmt, int nrhs, const std::vector<int64_t>* sys_bytes)
 {
     const int nsys = (int)sys.size();
     hipStream_t st = h.stream;
@@ -375,10 +386,10 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
     }
     if (h.opt.loop == 1) {
         void* fn = sweep_kernel(fp32, nrhs, colfmt, 1, keep);
-        const size_t lds = loop_lds_bytes(fp_bytes, runs, nsys);
+        const size_t lds = loop_lds_bytes(fp_bytes, tab, nsys);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, work);
         h.last_grid = grid;
-        launch_loop(fn, grid, block, lds, st, p, fp_bytes, runs, true);
+        launch_loop(fn, grid, block, lds, st, p, fp_bytes, tab, true);
     } else if (nsys > 1) {
         // One launch per sweep over the systems still running.  The host
         // reads the states one chunk of launches behind (so the device never
@@ -396,7 +407,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
             }
             return sweep_kernel(fp32, nrhs, colfmt, 2, kp);
         };
-        const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
+        const size_t lds = loop_lds_bytes(fp_bytes, tab, 0);
         const size_t wl_ints = 2 * (size_t)nsys + 1;
         const size_t host_bytes = (size_t)nsys * sizeof(SysState) + 2 * wl_ints * sizeof(int32_t);
         if (h.d.batch_host.bytes < host_bytes) {
@@ -439,7 +450,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         while (!all_done && k <= kend) {
             const int32_t e = std::min<int32_t>(kend + 1, k + chunk);
             const int32_t na = (int32_t)act.size();
-            for (; k < e; ++k) launch_sweep_multi(fn, items + na, block, lds, st, p, k, d_wl, na, fp_bytes, runs);
+            for (; k < e; ++k) launch_sweep_multi(fn, items + na, block, lds, st, p, k, d_wl, na, fp_bytes, tab);
             if (pending) {
                 JAC_HIP(hipEventSynchronize(h.pev));
                 std::vector<int32_t> next;
@@ -462,11 +473,11 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
         if (!all_done) launch_decide_multi(nrhs, st, p, kend);
     } else {
         void* fn = sweep_kernel(fp32, nrhs, colfmt, 0, keep);
-        const size_t lds = loop_lds_bytes(fp_bytes, runs, 0);
+        const size_t lds = loop_lds_bytes(fp_bytes, tab, 0);
         const int grid = sweep_grid(h, fn, block, lds);
         h.last_grid = grid;
         if (!solve) {
-            for (int32_t k = 0; k < kend; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);
+            for (int32_t k = 0; k < kend; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, tab);
             launch_decide(nrhs, st, p, kend - 1);
         } else {
             // Launch in chunks; while chunk j runs, look at the stop word copied
@@ -484,7 +495,7 @@ void run_loop(Handle& h, std::vector<SysDev>& sys, bool fp32, bool solve, int32_
             bool pending = false, stop = false;
             while (!stop && k <= kend) {
                 const int32_t e = std::min<int32_t>(kend + 1, k + chunk);
-                for (; k < e; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, runs);
+                for (; k < e; ++k) launch_sweep1(fn, grid, block, lds, st, p, k, fp_bytes, tab);
                 if (pending) {
                     JAC_HIP(hipEventSynchronize(h.pev));
                     if (poll[0] <= seen_upto) stop = true;
@@ -723,7 +734,7 @@ jac_status jac_sweep(jac_handle h, int32_t nsweeps, double* hist_dev)
         std::vector<SysDev> sys = {h->sysdev(false)};
         std::vector<int32_t> tb = {0, h->plan.ntiles};
         run_loop(*h, sys, false, false, nsweeps, 0, hist_dev, h->d.sys, h->d.state, h->d.tile_base, tb,
-                 h->lds_fp_bytes(false), h->lds_runs(), h->plan.colfmt, h->nrhs);
+                 h->lds_fp_bytes(false), h->lds_tab(), h->plan.colfmt, h->nrhs);
         uint32_t which = 0;
         for (int c = 0; c < h->nrhs; ++c) which |= (uint32_t)(nsweeps % 3) << (2 * c);
         h->settle(which);
@@ -745,7 +756,7 @@ static jac_status solve64(Handle& h, double tol, int32_t maxit, int norm, int32_
     std::vector<SysDev> sys = {s};
     std::vector<int32_t> tb = {0, h.plan.ntiles};
     run_loop(h, sys, false, true, maxit, norm == JAC_NORM_INF_ABS ? 1 : 0, nullptr, h.d.sys, h.d.state,
-             h.d.tile_base, tb, h.lds_fp_bytes(false), h.lds_runs(), h.plan.colfmt, h.nrhs);
+             h.d.tile_base, tb, h.lds_fp_bytes(false), h.lds_tab(), h.plan.colfmt, h.nrhs);
     SysState st;
     JAC_HIP(hipMemcpyAsync(&st, h.d.state.p, sizeof(SysState), hipMemcpyDeviceToHost, h.stream));
     h.sync();
@@ -790,7 +801,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         std::vector<SysDev> sys;
         std::vector<int32_t> tb = {0};
         std::vector<double> scale((size_t)nsys * 4, 1.0);
-        int fpb = 0, runs = 0;
+        int fpb = 0, tab = 0;
         for (int32_t s = 0; s < nsys; ++s) {
             if (!hs[s]) fail(JAC_E_INVALID, "NULL handle in batch");
             hs[s]->require_plan();
@@ -809,7 +820,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
             sys.push_back(d);
             tb.push_back(tb.back() + h.plan.ntiles);
             fpb = std::max(fpb, h.lds_fp_bytes(false));
-            runs = std::max(runs, h.lds_runs());
+            tab = std::max(tab, h.lds_tab());
         }
         // a sweep of the batch streams every running system: the persistent
         // launch decides once on the whole batch, the per-sweep launches
@@ -821,7 +832,7 @@ jac_status jac_solve_batched(const jac_handle* hs, int32_t nsys, double tol, int
         for (int32_t s = 1; s < nsys; ++s) hs[s]->sync();
         upload(h0.d.batch_tile_base, tb, h0.stream);
         run_loop(h0, sys, false, true, maxit, 0, nullptr, h0.d.batch_sys, h0.d.batch_state, h0.d.batch_tile_base, tb,
-                 fpb, runs, colfmt, nrhs, &bytes);
+                 fpb, tab, colfmt, nrhs, &bytes);
         std::vector<SysState> st((size_t)nsys);
         JAC_HIP(hipMemcpyAsync(st.data(), h0.d.batch_state.p, st.size() * sizeof(SysState), hipMemcpyDeviceToHost,
                                h0.stream));
@@ -944,7 +955,9 @@ jac_status jac_get_info(jac_handle h, jac_info* info)
         i.alg_bytes_per_sweep = 12 * nnz + 4 * (n + 1) + 8 * n + 24 * n * r;
         int64_t dev = h->plan.slots * 8 + (h->plan.slots - h->plan.table_slots) * i.col_bytes + 24 * n * r;
         dev += (int64_t)h->plan.nslices * (4 + 4 + 8) + (int64_t)(h->plan.table_slots / kSlice) * 4;
-        if (h->plan.prm.staged) dev += (h->plan.staged_entries - n) * 8 * r + (int64_t)h->plan.run_start.size() * 8;
+        if (h->plan.prm.staged)
+            dev += (h->plan.staged_entries - n) * 8 * r + (int64_t)h->plan.run_delta.size() * 8 +
+                   (int64_t)h->plan.chunk_bits.size() * 12;
         i.dev_bytes_per_sweep = dev;
         i.loop_grid = h->last_grid;
         i.block = h->opt.block;

@@ -53,8 +53,8 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
         const SysDev* dsys = static_cast<const SysDev*>(d.async_sys.p);
         void* fn = async_kernel(nr, h.plan.colfmt, s.keep != 0);
         const int block = h.opt.block;
-        const int fpb = h.lds_fp_bytes(false), runs = h.lds_runs();
-        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const int fpb = h.lds_fp_bytes(false), tab = h.lds_tab();
+        const size_t lds = loop_lds_bytes(fpb, tab, 0);
         const int grid = loop_grid(fn, block, lds, h.opt.wg_per_cu, std::max(h.plan.ntiles, 1));
         h.last_grid = grid;
         if (h.opt.timing) {
@@ -67,7 +67,7 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
         int status = JAC_OK;
         for (;;) {
             launch_resid(nr, h.plan.colfmt, std::max(h.plan.ntiles, 1), block, lds, st, dsys,
-                         static_cast<float*>(d.async_r32.p), 0u, norm_inf, fpb, runs);
+                         static_cast<float*>(d.async_r32.p), 0u, norm_inf, fpb, tab);
             launch_part_norm(nr, st, dsys, norm_inf, static_cast<double*>(d.async_norm.p));
             JAC_HIP(hipMemcpyAsync(nrm, d.async_norm.p, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
             h.sync();
@@ -86,7 +86,7 @@ extern "C" jac_status jac_solve_async(jac_handle hp, double tol, int32_t maxit, 
                 break;
             }
             const int32_t R = std::min(rounds_per_check, maxit - rounds);
-            launch_async(fn, grid, block, lds, st, dsys, R, fpb, runs);
+            launch_async(fn, grid, block, lds, st, dsys, R, fpb, tab);
             rounds += R;
         }
         if (h.opt.timing) {

@@ -54,7 +54,7 @@ int32_t keep_matrix(int32_t policy, int64_t bytes);
 
 struct DeviceArrays {
     DevMem tile_row0, tile_slice0, slice_row0, slice_width, slice_off;
-    DevMem col32, col16, tile_run0, run_start, run_lds, tile_fp, tile_own;
+    DevMem col32, col16, tile_run0, run_lds, run_delta, tile_chunk0, chunk_bits, chunk_run, tile_fp, tile_own;
     DevMem shift;                          // shift-table formats: shifts per slot column
     DevMem slot_of_caller, diag_slot, perm;
     DevMem vals_caller, b_caller;          // caller order, kept for re-planning
@@ -126,7 +126,7 @@ struct Handle {
     // until a jac_partition succeeds.
     void require_plan() const;
     int lds_fp_bytes(bool fp32) const;
-    int lds_runs() const;
+    int lds_tab() const;
 };
 
 int loop_grid(void* fn, int block, size_t lds, int wg_per_cu, int64_t work);

@@ -156,13 +156,18 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         pl.tile_run0.assign((size_t)pl.ntiles + 1, 0);
         pl.tile_fp.assign((size_t)pl.ntiles, 0);
         pl.tile_own.assign((size_t)pl.ntiles, 0);
+        pl.tile_chunk0.assign((size_t)pl.ntiles + 1, 0);
         pl.run_start.clear();
         pl.run_lds.clear();
+        pl.run_delta.clear();
+        pl.chunk_bits.clear();
+        pl.chunk_run.clear();
     } else if (!rel16 && !tables) {
         pl.col32.assign((size_t)pl.slots, 0);
     }
     pl.max_fp = 0;
     pl.max_runs = 0;
+    pl.max_tab = 0;
     pl.staged_entries = 0;
     for (int32_t t = 0; t < pl.ntiles; ++t) {
         const int32_t r0 = pl.tile_row0[t], r1 = pl.tile_row0[t + 1];
@@ -171,16 +176,33 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
         if (prm.staged) {
             cols = &fps[t].cols;
             pl.tile_run0[t] = (int32_t)pl.run_start.size();
+            pl.tile_chunk0[t] = (int32_t)pl.chunk_bits.size();
             for (size_t m = 0; m < cols->size(); ++m)
                 if (m == 0 || (*cols)[m] != (*cols)[m - 1] + 1) {
                     pl.run_start.push_back((*cols)[m]);
                     pl.run_lds.push_back((int32_t)m);
+                    pl.run_delta.push_back((*cols)[m] - (int32_t)m);
                 }
+            const int32_t nr = (int32_t)pl.run_start.size() - pl.tile_run0[t];
+            if (nr > kRegRuns) {
+                int32_t r = -1;
+                for (size_t m = 0; m < cols->size(); ++m) {
+                    const bool starts = r + 1 < nr && pl.run_lds[(size_t)pl.tile_run0[t] + r + 1] == (int32_t)m;
+                    if (starts) ++r;
+                    if ((m & 63) == 0) {
+                        pl.chunk_bits.push_back(0);
+                        pl.chunk_run.push_back(r);
+                    }
+                    if (starts) pl.chunk_bits.back() |= (uint64_t)1 << (m & 63);
+                }
+                const int32_t nch = (int32_t)pl.chunk_bits.size() - pl.tile_chunk0[t];
+                pl.max_tab = std::max(pl.max_tab, (3 * nch + nr + 1) & ~1);
+            }
             pl.tile_fp[t] = (int32_t)cols->size();
             own = (int32_t)(std::lower_bound(cols->begin(), cols->end(), r0) - cols->begin());
             pl.tile_own[t] = own;
             pl.max_fp = std::max(pl.max_fp, pl.tile_fp[t]);
-            pl.max_runs = std::max(pl.max_runs, (int32_t)pl.run_start.size() - pl.tile_run0[t]);
+            pl.max_runs = std::max(pl.max_runs, nr);
             pl.staged_entries += pl.tile_fp[t];
         }
         for (int32_t s = pl.tile_slice0[t]; s < pl.tile_slice0[t + 1]; ++s) {
@@ -236,7 +258,10 @@ Plan make_plan(const Csr& a, const std::vector<int32_t>& cuts_in, const PlanPara
             }
         }
     }
-    if (prm.staged) pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+    if (prm.staged) {
+        pl.tile_run0[pl.ntiles] = (int32_t)pl.run_start.size();
+        pl.tile_chunk0[pl.ntiles] = (int32_t)pl.chunk_bits.size();
+    }
     // tile cost spread: streamed bytes (about 10 per slot, 8 per staged
     // entry) plus 256 per footprint run, largest over mean
     {

@@ -77,6 +77,12 @@ struct PlanParams {
 // row + shift).
 enum ColFormat { COL_GLOBAL32 = 0, COL_REL16 = 1, COL_LOCAL16 = 2, COL_TABG = 3, COL_TABL = 4 };
 
+// A staged tile whose footprint has at most this many runs (a band of rows
+// with the neighbours below and above) finds an entry's run by comparisons
+// against run starts held in registers; a tile with more uses its chunk
+// table of run-start bits.
+constexpr int32_t kRegRuns = 4;
+
 struct Plan {
     PlanParams prm;
     int32_t ntiles = 0, nslices = 0;
@@ -95,9 +101,20 @@ struct Plan {
     std::vector<int32_t> tile_run0;   // ntiles + 1
     std::vector<int32_t> run_start;   // global column of each run
     std::vector<int32_t> run_lds;     // LDS offset of each run (per tile, from 0)
+    std::vector<int32_t> run_delta;   // run_start - run_lds: global column = LDS position + delta
     std::vector<int32_t> tile_fp;     // footprint entries per tile
     std::vector<int32_t> tile_own;    // LDS offset of the tile's own first row
+    // run lookup of tiles with more than kRegRuns runs, by chunks of 64
+    // footprint entries: bit j of chunk_bits[c] is set when entry 64c + j
+    // starts a run, chunk_run[c] is the run (from the tile's first) that
+    // holds entry 64c, so entry e lies in run chunk_run[e/64] + (runs
+    // starting in bits 1 .. e%64 of its chunk).  Tiles of at most kRegRuns
+    // runs have no chunks: the kernel holds their runs in registers.
+    std::vector<int32_t> tile_chunk0; // ntiles + 1
+    std::vector<uint64_t> chunk_bits;
+    std::vector<int32_t> chunk_run;
     int32_t max_fp = 0, max_runs = 0;
+    int32_t max_tab = 0;              // largest chunked tile's lookup table, int32 words: 3 a chunk + 1 a run, even
     int64_t staged_entries = 0;
     // largest tile cost over the mean, a tile's cost taken as the bytes it
     // streams (10 per slot, 8 per staged entry) plus 256 per footprint run

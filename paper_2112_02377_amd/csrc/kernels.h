@@ -20,8 +20,11 @@ struct SysDev {
     const int32_t* col32;     // global columns (unstaged)
     const uint16_t* col16;    // j - i as int16, or tile-local columns (staged)
     const int32_t* tile_run0;
-    const int32_t* run_start;
-    const int32_t* run_lds;
+    const int32_t* run_lds;   // staged: first LDS position of each footprint run
+    const int32_t* run_delta; // staged: global column minus LDS position, per footprint run
+    const int32_t* tile_chunk0;
+    const uint64_t* chunk_bits; // staged: run starts per 64 footprint entries
+    const int32_t* chunk_run;   // staged: run (from the tile's first) holding each chunk's first entry
     const int32_t* tile_fp;
     const int32_t* tile_own;
     const int32_t* shift;     // shift-table formats: one shift per slot column (slots / 64)

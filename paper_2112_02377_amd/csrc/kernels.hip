@@ -214,8 +214,8 @@ __device__ __forceinline__ void load_batch_clamped(gptr<const T> val, gptr<const
 
 template <typename T, int NRHS, int CM, bool NT, bool RESID = false, bool COH = false>
 __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const T* x_, T* xn_, uint32_t frozen,
-                                           bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_rs,
-                                           int32_t* __restrict__ lds_ro, double (&acc)[NRHS],
+                                           bool is_max, T* __restrict__ lds_x, int32_t* __restrict__ lds_tab,
+                                           double (&acc)[NRHS],
                                            float* rout_ = nullptr)
 {
     // RESID: no update; the residual is written rounded to FP32 into rout
@@ -245,52 +245,88 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
     // position) i + shift[slice_off[s] / 64 + k] of every row i of the slice
     constexpr bool TAB = CM == COL_TABG || CM == COL_TABL;
     if constexpr (STAGED) {
-        const gptr<const int32_t> run_start = (gptr<const int32_t>)D->run_start;
-        const gptr<const int32_t> run_lds = (gptr<const int32_t>)D->run_lds;
         const int32_t run0 = ((cptr<const int32_t>)D->tile_run0)[tile];
         const int32_t nr = ((cptr<const int32_t>)D->tile_run0)[tile + 1] - run0;
+        const int32_t ch0 = ((cptr<const int32_t>)D->tile_chunk0)[tile];
+        const int32_t nch = ((cptr<const int32_t>)D->tile_chunk0)[tile + 1] - ch0;
         const int32_t fp = ((cptr<const int32_t>)D->tile_fp)[tile];
         own = ((cptr<const int32_t>)D->tile_own)[tile];
         lim = fp;
-        for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) {
-            lds_rs[t] = run_start[run0 + t];
-            lds_ro[t] = run_lds[run0 + t];
-        }
-        __syncthreads();
-        // element e of the footprint lies in the last run starting at or
-        // before it: a binary search whose steps depend on nr only, so every
-        // lane takes the same ones and the SU searches of a batch interleave.
-        // A probe past the last run reads the last run instead, which can
-        // only move lo to the last run when that is the answer.  Lanes past
-        // the end of the footprint redo its last element: they load and store
-        // the same value to the same place as its own lane, so no load or
-        // store needs a predicate and the batch's loads issue together.
-        const int32_t top = nr > 1 ? (int32_t)(0x80000000u >> __builtin_clz((uint32_t)(nr - 1))) : 0;
-        for (int32_t e0 = threadIdx.x; e0 < fp; e0 += blockDim.x * SU) {
-            int32_t e[SU], lo[SU];
+        // Lanes past the end of the footprint redo its last entry: they load
+        // and store the same value to the same place as its own lane, so no
+        // load or store needs a predicate and the batch's loads issue together.
+        if (nch == 0) {
+            // at most kRegRuns runs: entry e lies in the last run whose first
+            // LDS position is at or below e; the runs' first positions and
+            // deltas (global column minus LDS position) sit in registers,
+            // absent runs start past the footprint
+            const cptr<const int32_t> rl = (cptr<const int32_t>)D->run_lds;
+            const cptr<const int32_t> rd = (cptr<const int32_t>)D->run_delta;
+            int32_t rs[kRegRuns], dl[kRegRuns];
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                e[u] = min(e0 + u * (int32_t)blockDim.x, fp - 1);
-                lo[u] = 0;
+            for (int q = 0; q < kRegRuns; ++q) {
+                const int32_t j = run0 + min(q, nr - 1);
+                rs[q] = q < nr ? rl[j] : fp;
+                dl[q] = rd[j];
             }
-            for (int32_t step = top; step > 0; step >>= 1) {
+            for (int32_t e0 = threadIdx.x; e0 < fp; e0 += blockDim.x * SU) {
+                int32_t e[SU];
+                T v[SU][NRHS];
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
-                    const int32_t t = min(lo[u] + step, nr - 1);
-                    lo[u] = lds_ro[t] <= e[u] ? t : lo[u];
+                    e[u] = min(e0 + u * (int32_t)blockDim.x, fp - 1);
+                    int32_t dd = dl[0];
+#pragma unroll
+                    for (int q = 1; q < kRegRuns; ++q) dd = e[u] >= rs[q] ? dl[q] : dd;
+                    const int64_t g = (int64_t)(dd + e[u]);
+#pragma unroll
+                    for (int c = 0; c < NRHS; ++c) v[u][c] = ldx<T, COH>(&x_[g * NRHS + c]);
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+#pragma unroll
+                    for (int c = 0; c < NRHS; ++c) lds_x[e[u] * NRHS + c] = v[u][c];
                 }
             }
-            T v[SU][NRHS];
-#pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                const int64_t g = (int64_t)(lds_rs[lo[u]] + (e[u] - lds_ro[lo[u]]));
-#pragma unroll
-                for (int c = 0; c < NRHS; ++c) v[u][c] = ldx<T, COH>(&x_[g * NRHS + c]);
+        } else {
+            // the tile's run lookup table: per 64 footprint entries a word of
+            // run-start bits and the run holding the first entry, then per
+            // run the global column minus the LDS position
+            uint64_t* lds_bits = reinterpret_cast<uint64_t*>(lds_tab);
+            int32_t* lds_crun = lds_tab + 2 * nch;
+            int32_t* lds_delta = lds_crun + nch;
+            {
+                const gptr<const uint64_t> bits = (gptr<const uint64_t>)D->chunk_bits;
+                const gptr<const int32_t> crun = (gptr<const int32_t>)D->chunk_run;
+                const gptr<const int32_t> delta = (gptr<const int32_t>)D->run_delta;
+                for (int32_t t = threadIdx.x; t < nch; t += blockDim.x) {
+                    lds_bits[t] = bits[ch0 + t];
+                    lds_crun[t] = crun[ch0 + t];
+                }
+                for (int32_t t = threadIdx.x; t < nr; t += blockDim.x) lds_delta[t] = delta[run0 + t];
             }
+            __syncthreads();
+            // entry e lies in run crun[e/64] plus the number of runs that
+            // start at bits 1 .. e%64 of its chunk's word (a run starting at
+            // bit 0 is the one crun names): two LDS reads and a popcount
+            for (int32_t e0 = threadIdx.x; e0 < fp; e0 += blockDim.x * SU) {
+                int32_t e[SU];
+                T v[SU][NRHS];
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
+                for (int u = 0; u < SU; ++u) {
+                    e[u] = min(e0 + u * (int32_t)blockDim.x, fp - 1);
+                    const int32_t c = e[u] >> 6;
+                    const uint64_t below = ((uint64_t)2 << (e[u] & 63)) - 2;
+                    const int32_t r = lds_crun[c] + __popcll(lds_bits[c] & below);
+                    const int64_t g = (int64_t)(lds_delta[r] + e[u]);
 #pragma unroll
-                for (int c = 0; c < NRHS; ++c) lds_x[e[u] * NRHS + c] = v[u][c];
+                    for (int c2 = 0; c2 < NRHS; ++c2) v[u][c2] = ldx<T, COH>(&x_[g * NRHS + c2]);
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+#pragma unroll
+                    for (int c = 0; c < NRHS; ++c) lds_x[e[u] * NRHS + c] = v[u][c];
+                }
             }
         }
         __syncthreads();
@@ -439,14 +475,13 @@ __device__ void decide(const LoopParams& P, int32_t s, int32_t k, const SysDev& 
 template <typename T, int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(NRHS == 1 && sizeof(T) == 8 && (CM == COL_TABG || CM == COL_TABL) ? 8 : 1)))
-k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
+k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t tab_words)
 {
     extern __shared__ __align__(16) char smem[];
     const SysDev& S = P.sys[0];
     T* lds_x = reinterpret_cast<T*>(smem);
-    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
-    int32_t* lds_ro = lds_rs + lds_runs;
-    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t* lds_tab = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    double* red = reinterpret_cast<double*>(lds_tab + tab_words);
     if (blockIdx.x == gridDim.x - 1) {
         if (k > P.k0) decide<NRHS, false>(P, 0, k - 1, S, red);
         return;
@@ -483,7 +518,7 @@ k_sweep(LoopParams P, int32_t k, int32_t lds_fp_bytes, int32_t lds_runs)
         double acc[NRHS];
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-        sweep_tile<T, NRHS, CM, NT>(S, tile, x, xn, frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+        sweep_tile<T, NRHS, CM, NT>(S, tile, x, xn, frozen, is_max, lds_x, lds_tab, acc);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -510,13 +545,12 @@ __global__ void __launch_bounds__(512) k_decide(LoopParams P, int32_t k)
 // the list a little later).
 template <typename T, int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, const int32_t* __restrict__ wl,
-                                                    int32_t nact, int32_t lds_fp_bytes, int32_t lds_runs)
+                                                    int32_t nact, int32_t lds_fp_bytes, int32_t tab_words)
 {
     extern __shared__ __align__(16) char smem[];
     T* lds_x = reinterpret_cast<T*>(smem);
-    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
-    int32_t* lds_ro = lds_rs + lds_runs;
-    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t* lds_tab = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    double* red = reinterpret_cast<double*>(lds_tab + tab_words);
     const cptr<const int32_t> ids = (cptr<const int32_t>)wl;
     const cptr<const int32_t> pref = (cptr<const int32_t>)(wl + nact);
     const int32_t items = pref[nact];
@@ -547,7 +581,7 @@ __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, co
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
         sweep_tile<T, NRHS, CM, NT>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
-                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs, lds_ro, acc);
+                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_tab, acc);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
             double* part = S.tile_part + (int64_t)(k & 1) * S.ntiles * NRHS;
@@ -566,12 +600,11 @@ __global__ void __launch_bounds__(512) k_sweep_multi(LoopParams P, int32_t k, co
 // the quiescent x between launches.
 template <int NRHS, int CM, bool NT>
 __global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds, int32_t lds_fp_bytes,
-                                              int32_t lds_runs)
+                                              int32_t tab_words)
 {
     extern __shared__ __align__(16) char smem[];
     double* lds_x = reinterpret_cast<double*>(smem);
-    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
-    int32_t* lds_ro = lds_rs + lds_runs;
+    int32_t* lds_tab = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
     const SysDev& S = *sys;
     double* x = static_cast<double*>(S.x[0]);
     int32_t first, end, stride;
@@ -581,7 +614,7 @@ __global__ void __launch_bounds__(512) k_async(const SysDev* sys, int32_t rounds
             double acc[NRHS];
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
-            sweep_tile<double, NRHS, CM, NT, false, true>(S, tile, x, x, 0u, false, lds_x, lds_rs, lds_ro, acc);
+            sweep_tile<double, NRHS, CM, NT, false, true>(S, tile, x, x, 0u, false, lds_x, lds_tab, acc);
             if constexpr (CM == COL_LOCAL16 || CM == COL_TABL) __syncthreads();   // the next tile restages the LDS
         }
 }
@@ -604,14 +637,13 @@ __global__ void __launch_bounds__(512) k_decide_multi(LoopParams P, int32_t k)
 // ---------------------------------------------------------------------------
 template <int NRHS, int CM>
 __global__ void __launch_bounds__(512) k_resid(const SysDev* sys, float* r32, uint32_t frozen, int32_t norm_inf,
-                                              int32_t lds_fp_bytes, int32_t lds_runs)
+                                              int32_t lds_fp_bytes, int32_t tab_words)
 {
     extern __shared__ __align__(16) char smem[];
     const SysDev& S = *sys;
     double* lds_x = reinterpret_cast<double*>(smem);
-    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
-    int32_t* lds_ro = lds_rs + lds_runs;
-    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t* lds_tab = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    double* red = reinterpret_cast<double*>(lds_tab + tab_words);
     int32_t first, end, stride;
     xcd_items(S.ntiles, gridDim.x, blockIdx.x, first, end, stride);
     const bool is_max = norm_inf != 0;
@@ -620,7 +652,7 @@ __global__ void __launch_bounds__(512) k_resid(const SysDev* sys, float* r32, ui
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
         sweep_tile<double, NRHS, CM, true, true>(S, tile, reinterpret_cast<const double*>(S.x[0]), nullptr, frozen,
-                                                 is_max, lds_x, lds_rs, lds_ro, acc, r32);
+                                                 is_max, lds_x, lds_tab, acc, r32);
         block_reduce<NRHS>(acc, is_max, red);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -742,13 +774,12 @@ __device__ int32_t build_work(const LoopParams& P, int32_t k, int32_t* pref, int
 // (C) tiles; (D) barrier.  The third iterate buffer keeps x_k intact while
 // sweep k+1 runs before the decision on r_k is known.
 template <typename T, int NRHS, int CM, bool NT>
-__global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t lds_runs)
+__global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes, int32_t tab_words)
 {
     extern __shared__ __align__(16) char smem[];
     T* lds_x = reinterpret_cast<T*>(smem);
-    int32_t* lds_rs = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
-    int32_t* lds_ro = lds_rs + lds_runs;
-    double* red = reinterpret_cast<double*>(lds_ro + lds_runs);
+    int32_t* lds_tab = reinterpret_cast<int32_t*>(smem + lds_fp_bytes);
+    double* red = reinterpret_cast<double*>(lds_tab + tab_words);
     int32_t* flag = reinterpret_cast<int32_t*>(red + 16 * 4);
     int32_t* pref = flag + 4;
     int32_t* wsum = pref + P.nsys + 1;
@@ -779,7 +810,7 @@ __global__ void __launch_bounds__(512) k_loop(LoopParams P, int32_t lds_fp_bytes
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) acc[c] = 0.0;
             sweep_tile<T, NRHS, CM, NT>(S, tile, reinterpret_cast<const T*>(S.x[k % 3]),
-                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_rs, lds_ro,
+                                    reinterpret_cast<T*>(S.x[(k + 1) % 3]), frozen, is_max, lds_x, lds_tab,
                                     acc);
             block_reduce<NRHS>(acc, is_max, red);
             if (threadIdx.x == 0) {
@@ -957,15 +988,15 @@ void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop, bool keep)
     return f;
 }
 
-size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys)
+size_t loop_lds_bytes(int lds_fp_bytes, int lds_tab, int nsys)
 {
-    return (size_t)lds_fp_bytes + 2u * lds_runs * 4u + 16u * 4u * 8u + 16u + (size_t)(nsys + 1) * 4u + 16u * 4u;
+    return (size_t)lds_fp_bytes + (size_t)lds_tab * 4u + 16u * 4u * 8u + 16u + (size_t)(nsys + 1) * 4u + 16u * 4u;
 }
 
 void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int lds_fp_bytes,
-                 int lds_runs, bool cooperative)
+                 int lds_tab, bool cooperative)
 {
-    void* args[] = {&p, &lds_fp_bytes, &lds_runs};
+    void* args[] = {&p, &lds_fp_bytes, &lds_tab};
     if (cooperative)
         JAC_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, st));
     else
@@ -973,16 +1004,16 @@ void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, Loop
 }
 
 void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
-                   int lds_fp_bytes, int lds_runs)
+                   int lds_fp_bytes, int lds_tab)
 {
-    void* args[] = {&p, &k, &lds_fp_bytes, &lds_runs};
+    void* args[] = {&p, &k, &lds_fp_bytes, &lds_tab};
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 
 void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
-                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs)
+                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_tab)
 {
-    void* args[] = {&p, &k, &wl, &nact, &lds_fp_bytes, &lds_runs};
+    void* args[] = {&p, &k, &wl, &nact, &lds_fp_bytes, &lds_tab};
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 
@@ -1020,9 +1051,9 @@ void* async_kernel(int nrhs, int colfmt, bool keep)
 }
 
 void launch_async(void* fn, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys, int rounds,
-                  int lds_fp_bytes, int lds_runs)
+                  int lds_fp_bytes, int lds_tab)
 {
-    void* args[] = {&sys, &rounds, &lds_fp_bytes, &lds_runs};
+    void* args[] = {&sys, &rounds, &lds_fp_bytes, &lds_tab};
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 
@@ -1049,11 +1080,11 @@ void* resid_fn(int colfmt)
 }
 
 void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
-                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs)
+                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_tab)
 {
     void* fn = nrhs == 1 ? resid_fn<1>(colfmt) : (nrhs == 2 ? resid_fn<2>(colfmt) : resid_fn<4>(colfmt));
     int32_t ni = norm_inf;
-    void* args[] = {&sys, &r32, &frozen, &ni, &lds_fp_bytes, &lds_runs};
+    void* args[] = {&sys, &r32, &frozen, &ni, &lds_fp_bytes, &lds_tab};
     JAC_HIP(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st));
 }
 

@@ -14,23 +14,23 @@ namespace jac {
 // (1, 2 or 4), column format (ColFormat) and loop kind (0 = one launch per
 // sweep, 1 = persistent loop, 2 = one launch per sweep over a system list).
 void* sweep_kernel(bool fp32, int nrhs, int colfmt, int loop, bool keep);
-size_t loop_lds_bytes(int lds_fp_bytes, int lds_runs, int nsys);
+size_t loop_lds_bytes(int lds_fp_bytes, int lds_tab, int nsys);
 void launch_loop(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int lds_fp_bytes,
-                 int lds_runs, bool cooperative);
+                 int lds_tab, bool cooperative);
 void launch_sweep1(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
-                   int lds_fp_bytes, int lds_runs);
+                   int lds_fp_bytes, int lds_tab);
 void launch_decide(int nrhs, hipStream_t st, LoopParams p, int k);
 // several systems: wl = running system ids [nact] then their tile prefix [nact + 1]
 void launch_sweep_multi(void* fn, int grid, int block, size_t lds, hipStream_t st, LoopParams p, int k,
-                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_runs);
+                        const int32_t* wl, int nact, int lds_fp_bytes, int lds_tab);
 void launch_decide_multi(int nrhs, hipStream_t st, LoopParams p, int k);
 // asynchronous relaxation: `rounds` in-place passes over the tiles, x = sys->x[0]
 void* async_kernel(int nrhs, int colfmt, bool keep);
 void launch_async(void* fn, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys, int rounds,
-                  int lds_fp_bytes, int lds_runs);
+                  int lds_fp_bytes, int lds_tab);
 // mixed-precision refinement
 void launch_resid(int nrhs, int colfmt, int grid, int block, size_t lds, hipStream_t st, const SysDev* sys,
-                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_runs);
+                  float* r32, uint32_t frozen, int norm_inf, int lds_fp_bytes, int lds_tab);
 void launch_part_norm(int nrhs, hipStream_t st, const SysDev* sys, int norm_inf, double* out);
 void launch_add_correction(double* x, const float* d0, const float* d1, const float* d2, int32_t n, int32_t nrhs,
                            uint32_t which, uint32_t active, hipStream_t st);

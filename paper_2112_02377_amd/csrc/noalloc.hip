@@ -102,13 +102,13 @@ extern "C" jac_status jac_sweep_noalloc(jac_handle h, int32_t nsweeps, double* h
         p.kend = nsweeps;
         p.solve = 0;
         p.norm_inf = 0;
-        const int fpb = h->lds_fp_bytes(false), runs = h->lds_runs();
+        const int fpb = h->lds_fp_bytes(false), tab = h->lds_tab();
         void* fn = sweep_kernel(false, h->nrhs, h->plan.colfmt, 0, s.keep != 0);
-        const size_t lds = loop_lds_bytes(fpb, runs, 0);
+        const size_t lds = loop_lds_bytes(fpb, tab, 0);
         const int grid = sweep_grid(*h, fn, h->opt.block, lds);
         h->last_grid = grid;
         h->last_loop_sweeps = nsweeps;
-        for (int32_t k = 0; k < nsweeps; ++k) launch_sweep1(fn, grid, h->opt.block, lds, st, p, k, fpb, runs);
+        for (int32_t k = 0; k < nsweeps; ++k) launch_sweep1(fn, grid, h->opt.block, lds, st, p, k, fpb, tab);
         launch_decide(h->nrhs, st, p, nsweeps - 1);
         uint32_t which = 0;
         for (int c = 0; c < h->nrhs; ++c) which |= (uint32_t)(nsweeps % 3) << (2 * c);

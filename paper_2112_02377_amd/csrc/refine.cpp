@@ -66,14 +66,14 @@ jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t*
     uint32_t done = 0;
     int status = JAC_OK;
     const int block = h.opt.block;
-    const int fpb64 = h.lds_fp_bytes(false), fpb32 = h.lds_fp_bytes(true), runs = h.lds_runs();
-    const size_t lds64 = loop_lds_bytes(fpb64, runs, 0);
+    const int fpb64 = h.lds_fp_bytes(false), fpb32 = h.lds_fp_bytes(true), tab = h.lds_tab();
+    const size_t lds64 = loop_lds_bytes(fpb64, tab, 0);
     int32_t inner_sweeps_run = 0;
     double t_inner_ms = 0.0;
     for (int outer = 0;; ++outer) {
         launch_resid(nr, h.plan.colfmt, std::max(h.plan.ntiles, 1), block, lds64, h.stream,
                      static_cast<const SysDev*>(d_s64.p), static_cast<float*>(h.d.r32.p), done, norm_inf, fpb64,
-                     runs);
+                     tab);
         launch_part_norm(nr, h.stream, static_cast<const SysDev*>(d_s64.p), norm_inf,
                          static_cast<double*>(h.d.rpart.p));
         double nrm[4] = {0, 0, 0, 0};
@@ -117,7 +117,7 @@ jac_status solve_refine(Handle& h, double tol, int32_t maxit, int norm, int32_t*
         budget = std::max(budget, 1);
         std::vector<SysDev> sys = {s32};
         std::vector<int32_t> tb = {0, h.plan.ntiles};
-        run_loop(h, sys, true, true, budget, norm_inf, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, fpb32, runs,
+        run_loop(h, sys, true, true, budget, norm_inf, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, fpb32, tab,
                  h.plan.colfmt, nr);
         t_inner_ms += h.last_loop_ms;
         SysState st;

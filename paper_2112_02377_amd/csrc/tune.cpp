@@ -85,10 +85,10 @@ double time_sweeps(Handle& h, int32_t sweeps)
     const int32_t timing = h.opt.timing;
     h.opt.timing = 0;
     run_loop(h, sys, false, false, 2, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb, h.lds_fp_bytes(false),
-             h.lds_runs(), h.plan.colfmt, h.nrhs);
+             h.lds_tab(), h.plan.colfmt, h.nrhs);
     h.opt.timing = 1;
     run_loop(h, sys, false, false, sweeps, 0, nullptr, h.d.sys, h.d.state, h.d.tile_base, tb,
-             h.lds_fp_bytes(false), h.lds_runs(), h.plan.colfmt, h.nrhs);
+             h.lds_fp_bytes(false), h.lds_tab(), h.plan.colfmt, h.nrhs);
     h.opt.timing = timing;
     return h.last_loop_ms;
 }

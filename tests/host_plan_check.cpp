@@ -117,6 +117,33 @@ int main(int argc, char** argv)
                 if (c != pa.ci[p]) return bad("column", p, c);
                 if (pa.ci[p] == i && pl.diag_slot[i] != q) return bad("diagonal slot", i, q);
             }
+        // the sweep kernel's run lookup (chunk bits, chunk run, run delta)
+        // names the same global column as the run list for every footprint
+        // entry, and the largest table fits the size the launches reserve
+        if (prm.staged)
+            for (int32_t t = 0; t < pl.ntiles; ++t) {
+                const int32_t fp = pl.tile_fp[t], ch0 = pl.tile_chunk0[t], r0 = pl.tile_run0[t];
+                const int32_t nch = pl.tile_chunk0[t + 1] - ch0, nr = pl.tile_run0[t + 1] - r0;
+                const bool chunked = nr > kRegRuns;
+                if (nch != (chunked ? (fp + 63) / 64 : 0)) return bad("chunks", t, nch);
+                if (chunked && (3 * nch + nr) > pl.max_tab) return bad("table words", t, 3 * nch + nr);
+                int32_t r = r0;
+                for (int32_t e = 0; e < fp; ++e) {
+                    while (r + 1 < pl.tile_run0[t + 1] && pl.run_lds[r + 1] <= e) ++r;
+                    int32_t q = 0;
+                    if (chunked) {
+                        const uint64_t w = pl.chunk_bits[(size_t)ch0 + e / 64];
+                        const uint64_t below = ((uint64_t)2 << (e & 63)) - 2;
+                        q = pl.chunk_run[(size_t)ch0 + e / 64] + __builtin_popcountll(w & below);
+                    } else {
+                        for (int32_t k = 1; k < kRegRuns; ++k)
+                            if (k < nr && e >= pl.run_lds[(size_t)r0 + k]) q = k;
+                    }
+                    if (q < 0 || q >= nr) return bad("run lookup", t, q);
+                    if (pl.run_delta[(size_t)r0 + q] + e != pl.run_start[r] + (e - pl.run_lds[r]))
+                        return bad("run lookup column", t, e);
+                }
+            }
         for (int x = 0; x < 8; ++x)
             if (pl.xcd_tile0[x] > pl.xcd_tile0[x + 1]) return bad("XCD ranges", x, pl.xcd_tile0[x]);
         if (pl.xcd_tile0[0] != 0 || pl.xcd_tile0[8] != pl.ntiles) return bad("XCD ends", pl.xcd_tile0[8], pl.ntiles);
