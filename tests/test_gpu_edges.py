@@ -2,8 +2,9 @@
 
 Tile shapes at their limits (64-row tiles, one tile for the whole system,
 more waves than slices), LDS too small to stage (the planner then sweeps
-unstaged), a one-row system, zero sweeps, maxit = 0, and the arguments the
-library rejects.  Iterates are bit-identical under every tile shape: each row
+unstaged), staged tiles on both sides of the run count where the footprint
+lookup changes, a one-row system, zero sweeps, maxit = 0, and the arguments
+the library rejects.  Iterates are bit-identical under every tile shape: each row
 accumulates its entries in the same order whatever the tiling; only the norm's
 summation order changes."""
 import numpy as np
@@ -146,3 +147,66 @@ def test_lds_budget_bounds_staged_footprints_for_four_columns(mode, sub):
         for hist, x in out:
             assert rel_inf(x[c], xr) <= 1e-12, c
             assert np.all(np.abs(hist[:, c] - hr) <= 1e-12 * hr), c
+
+
+def runs_system(T=96, stride=1024, seed=5):
+    """Rows of 64-row tile t reference their neighbours i +- 1 and, for
+    j = 1 .. t mod 6, column (i + j * stride) mod n: a 64-row tile's staged
+    footprint is then 1 + (t mod 6) runs (its own rows with their two
+    neighbours, and one block of 64 per far shift), on both sides of the
+    four runs up to which the sweep keeps a tile's runs in registers."""
+    n = 64 * T
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        c = [i - 1, i + 1] + [(i + j * stride) % n for j in range(1, (i // 64) % 6 + 1)]
+        c = [v for v in c if 0 <= v < n]
+        rows += [i] * len(c)
+        cols += c
+    import scipy.sparse as sp
+    off = sp.csr_matrix((-rng.uniform(0.5, 1.0, len(rows)), (rows, cols)), shape=(n, n))
+    off.sum_duplicates()
+    A = (off + sp.diags(np.asarray(abs(off).sum(axis=1)).ravel() + 0.5)).tocsr()
+    A.sort_indices()
+    return W.CSRSystem(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data, rng.uniform(-1, 1, (1, n)))
+
+
+@pytest.mark.parametrize("tables", [1, 0])
+def test_staged_tiles_of_one_to_six_footprint_runs(tables):
+    # 64-row tiles of 1 .. 6 runs, both run lookups in one launch (registers
+    # up to four runs, the chunk table beyond): sweeps bit-identical to the
+    # unstaged split, whose rows add the same entries in the same order, and
+    # to the oracle to rounding; the persistent loop's solve bit-identical
+    # to the per-sweep launches'
+    need_gpu()
+    b = B()
+    s = runs_system()
+    K = 12
+    opts = {b.JAC_OPT_TILE_ROWS: 64, b.JAC_OPT_SHIFT_TABLES: tables}
+    hj = make(s, 1, 1, opts=opts)
+    hs = make(s, 2, 1, opts=opts)
+    info = b.jac_get_info(hs)
+    assert info["ntiles"] == 96 and info["col_format"] == (4 if tables else 2)   # staged: shift table or local columns
+    # footprint entries: 66 for the own rows and their neighbours (65 at the
+    # two ends), plus 64 per far shift
+    fp = sum(66 + 64 * (t % 6) for t in range(96)) - 2
+    assert info["staged_entries"] == fp, info["staged_entries"]
+    out = []
+    for h in (hj, hs):
+        out.append((sweep(h, K), get_x(h, s.n)[0]))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    _, xr, hr = ref.sweeps(s.row_ptr, s.col_idx, s.vals, s.b[0], K)
+    assert rel_inf(out[1][1], xr) <= 1e-12
+    assert np.all(np.abs(out[1][0][:, 0] - hr) <= 1e-12 * hr)
+    res = []
+    for loop in (0, 1):
+        b.jac_set_option(hs, b.JAC_OPT_LOOP, loop)
+        b.jac_set_x(hs, None)
+        st, sw, rr = b.jac_solve(hs, 1e-10, 5000)
+        assert st == b.JAC_OK
+        res.append((int(sw[0]), get_x(hs, s.n)[0]))
+    assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
+    sto, xo, ko, _ = ref.solve(s.row_ptr, s.col_idx, s.vals, s.b[0], 1e-10, 5000)
+    assert res[0][0] == ko and rel_inf(res[0][1], xo) <= 1e-10
+    b.jac_destroy(hj)
+    b.jac_destroy(hs)
