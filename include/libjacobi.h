@@ -82,8 +82,9 @@ typedef enum {
     JAC_OPT_LDS_ELEMS = 3,   /* max x entries staged per tile (LDS), default 4096;
                                 the split bounds it further so that a tile's
                                 staged footprint (nrhs doubles per entry), its
-                                runs and the reduction scratch fit the device's
-                                LDS per workgroup (160 KiB on gfx950)          */
+                                run lookup table and the reduction scratch fit
+                                the device's LDS per workgroup (160 KiB on
+                                gfx950)                                        */
     JAC_OPT_LOOP = 4,        /* 0 = one launch per sweep (default), 1 = persistent
                                 cooperative loop with a grid barrier per sweep     */
     JAC_OPT_WG_PER_CU = 5,   /* persistent loop: workgroups per CU, default 2 (0 =
