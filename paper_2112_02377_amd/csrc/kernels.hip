@@ -174,12 +174,12 @@ __device__ __forceinline__ V ldm(gptr<const V> p)
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
-template <bool NT, typename T, int CM>
+template <bool NT, typename T, int CM, int NB>
 __device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t> col32, gptr<const uint16_t> col16,
-                                           int64_t off, int32_t k0, int32_t w, T (&a)[KB], int32_t (&raw)[KB])
+                                           int64_t off, int32_t k0, int32_t w, T (&a)[NB], int32_t (&raw)[NB])
 {
 #pragma unroll
-    for (int u = 0; u < KB; ++u)
+    for (int u = 0; u < NB; ++u)
         if (k0 + u < w) {
             const int64_t slot = off + (int64_t)(k0 + u) * 64;
             a[u] = ldm<NT>(&val[slot]);
@@ -196,13 +196,13 @@ __device__ __forceinline__ void load_batch(gptr<const T> val, gptr<const int32_t
 // load, gather and multiply-add of the batch is issued without a branch
 // around it.  (The FP32 sweep keeps the guarded batch: the clamped one costs
 // it a wave per SIMD.)
-template <bool NT, typename T, int CM>
+template <bool NT, typename T, int CM, int NB>
 __device__ __forceinline__ void load_batch_clamped(gptr<const T> val, gptr<const int32_t> col32,
                                                    gptr<const uint16_t> col16, int64_t off, int32_t k0, int32_t w,
-                                                   T (&a)[KB], int32_t (&raw)[KB])
+                                                   T (&a)[NB], int32_t (&raw)[NB])
 {
 #pragma unroll
-    for (int u = 0; u < KB; ++u) {
+    for (int u = 0; u < NB; ++u) {
         const int64_t slot = off + (int64_t)min(k0 + u, w - 1) * 64;
         a[u] = ldm<NT>(&val[slot]);
         if constexpr (CM == COL_GLOBAL32) raw[u] = ldm<NT>(&col32[slot]);
@@ -349,20 +349,33 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         T d = (T)1;                               // diagonal, found among the row's entries
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) { q[c] = Vec<T>::zero(); xi[c] = Vec<T>::zero(); }
+        // Four right-hand sides: b is loaded before the slot loop, so that
+        // it arrives with the slots' loads instead of a round trip after them
+        // (lanes past the tile's last row load that row's b and use none of it)
+        constexpr bool PREB = NRHS == 4 && sizeof(T) == 8;
+        // slots per batch: four FP64 right-hand sides hold 8 registers per
+        // gathered slot, and 7 slots cover a 7-point row in one batch
+        constexpr int NB = PREB ? 7 : KB;
+        T bv[NRHS];
+        if constexpr (PREB) {
+            const int64_t ib = (int64_t)min(i, r1 - 1) * NRHS;
+#pragma unroll
+            for (int c = 0; c < NRHS; ++c) bv[c] = b[ib + c];
+        }
         const int32_t self = STAGED ? own + (i - r0) : i;   // column index of the diagonal
         const int64_t sbase = soff >> 6;                    // the slice's first shift
-        for (int32_t k0 = 0; k0 < w; k0 += KB) {
+        for (int32_t k0 = 0; k0 < w; k0 += NB) {
             // all value / column loads of the batch first, decoded afterwards,
             // so that none waits for another
             constexpr bool BF = sizeof(T) == 8;
-            T a[KB];
-            int32_t raw[KB];
+            T a[NB];
+            int32_t raw[NB];
             if constexpr (BF) load_batch_clamped<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
             else load_batch<NT, T, CM>(val, col32, col16, off, k0, w, a, raw);
-            int32_t col[KB];
-            T xv[KB][NRHS];
+            int32_t col[NB];
+            T xv[NB][NRHS];
 #pragma unroll
-            for (int u = 0; u < KB; ++u) {
+            for (int u = 0; u < NB; ++u) {
                 if (!BF && k0 + u >= w) continue;
                 const int32_t ku = min(k0 + u, w - 1);
                 // a table slot that a row does not use holds a zero: its
@@ -377,12 +390,19 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
                 if (k0 + u >= w) a[u] = (T)0;            // slot past the width: adds nothing
             }
 #pragma unroll
-            for (int u = 0; u < KB; ++u) {
+            for (int u = 0; u < NB; ++u) {
                 if (!BF && k0 + u >= w) continue;
 #pragma unroll
                 for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
-                // the stored diagonal is nonzero; padding slots hold 0
-                if (col[u] == self && a[u] != (T)0) {
+                // the stored diagonal is nonzero; padding slots hold 0.  With
+                // four right-hand sides a shift table's diagonal is found as
+                // its slot of shift self - i (the same for every row of the
+                // tile), so that the gathered columns need not stay live:
+                // that keeps the sweep within 128 registers, 4 waves per SIMD
+                bool diag;
+                if constexpr (TAB && PREB) diag = shift[sbase + min(k0 + u, w - 1)] == self - i;
+                else diag = col[u] == self;
+                if (diag && a[u] != (T)0) {
                     d = a[u];
 #pragma unroll
                     for (int c = 0; c < NRHS; ++c) xi[c] = xv[u][c];
@@ -395,7 +415,7 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
             const T di = (T)1 / d;
 #pragma unroll
             for (int c = 0; c < NRHS; ++c) {
-                const T r = b[(int64_t)i * NRHS + c] - q[c];
+                const T r = (PREB ? bv[c] : b[(int64_t)i * NRHS + c]) - q[c];
                 if constexpr (RESID) rout[(int64_t)i * NRHS + c] = ((frozen >> c) & 1u) ? 0.0f : (float)r;
                 else if (!((frozen >> c) & 1u)) {
                     if constexpr (COH) stx_dev(&xn_[(int64_t)i * NRHS + c], xi[c] + di * r);
