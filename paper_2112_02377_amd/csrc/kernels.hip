@@ -349,13 +349,17 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         T d = (T)1;                               // diagonal, found among the row's entries
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) { q[c] = Vec<T>::zero(); xi[c] = Vec<T>::zero(); }
-        // Four right-hand sides: b is loaded before the slot loop, so that
-        // it arrives with the slots' loads instead of a round trip after them
-        // (lanes past the tile's last row load that row's b and use none of it)
-        constexpr bool PREB = NRHS == 4 && sizeof(T) == 8;
-        // slots per batch: four FP64 right-hand sides hold 8 registers per
-        // gathered slot, and 7 slots cover a 7-point row in one batch
-        constexpr int NB = PREB ? 7 : KB;
+        // FP64 with four right-hand sides or tile-local columns: b is loaded
+        // before the slot loop, so that it arrives with the slots' loads
+        // instead of a round trip after them (lanes past the tile's last row
+        // load that row's b and use none of it).  Both kernels have the
+        // registers to spare at their occupancy; the shift-table sweeps of
+        // one right-hand side do not.
+        constexpr bool PREB = sizeof(T) == 8 && (NRHS == 4 || (NRHS == 1 && CM == COL_LOCAL16));
+        // Slots per batch: 7 (a 7-point row in one batch, a 27-point row in
+        // four with one padding slot) where measured faster than 8 — these
+        // kernels and the staged shift table; the unstaged shift table keeps 8
+        constexpr int NB = PREB || (sizeof(T) == 8 && CM == COL_TABL) ? 7 : KB;
         T bv[NRHS];
         if constexpr (PREB) {
             const int64_t ib = (int64_t)min(i, r1 - 1) * NRHS;
