@@ -1243,6 +1243,16 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
             const int32_t w = (int32_t)((slice_off[s + 1] - soff) >> 6);
             const int64_t off = soff + lane;
             const int32_t i = row0 + lane;
+            // the row's own operands are loaded before the slot loop, so that
+            // they arrive with its loads (lanes past the tile's last row read
+            // that row's and write nothing)
+            const int32_t ib = min(i, r1 - 1);
+            const double lin = lam_in[ib];
+            double dinv = 0.0, g0 = 0.0;
+            if (mu_out) {
+                dinv = invd[ib];
+                g0 = gb[ib];
+            }
             double q = 0.0;
             for (int32_t k0 = 0; k0 < w; k0 += KB) {
                 double a[KB];
@@ -1257,12 +1267,12 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
                     if (k0 + u < w) q = __builtin_fma(a[u], mv[u], q);
             }
             if (i < r1) {
-                const double l = lam_in[i] - q;
+                const double l = lin - q;
                 lam_out[i] = l;
                 if (mu_out) {
-                    const double m = invd[i] * l;
+                    const double m = dinv * l;
                     mu_out[i] = m;
-                    gb[i] += m;
+                    gb[i] = g0 + m;
                 }
             }
         }
