@@ -349,17 +349,15 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
         T d = (T)1;                               // diagonal, found among the row's entries
 #pragma unroll
         for (int c = 0; c < NRHS; ++c) { q[c] = Vec<T>::zero(); xi[c] = Vec<T>::zero(); }
-        // FP64 with four right-hand sides or tile-local columns: b is loaded
-        // before the slot loop, so that it arrives with the slots' loads
-        // instead of a round trip after them (lanes past the tile's last row
-        // load that row's b and use none of it).  Both kernels have the
-        // registers to spare at their occupancy; the shift-table sweeps of
-        // one right-hand side do not.
-        constexpr bool PREB = sizeof(T) == 8 && (NRHS == 4 || (NRHS == 1 && CM == COL_LOCAL16));
-        // Slots per batch: 7 (a 7-point row in one batch, a 27-point row in
-        // four with one padding slot) where measured faster than 8 — these
-        // kernels and the staged shift table; the unstaged shift table keeps 8
-        constexpr int NB = PREB || (sizeof(T) == 8 && CM == COL_TABL) ? 7 : KB;
+        // FP64 with one or four right-hand sides: b is loaded before the slot
+        // loop, so that it arrives with the slots' loads instead of a round
+        // trip after them (lanes past the tile's last row load that row's b
+        // and use none of it).  The FP32 sweeps keep it after the loop (with
+        // it before, the compiler serialises their batch's loads).
+        constexpr bool PREB = sizeof(T) == 8 && (NRHS == 4 || NRHS == 1);
+        // Slots per batch: 7 for FP64 (a 7-point row in one batch, a 27-point
+        // row in four with one padding slot), 8 for FP32
+        constexpr int NB = sizeof(T) == 8 ? 7 : KB;
         T bv[NRHS];
         if constexpr (PREB) {
             const int64_t ib = (int64_t)min(i, r1 - 1) * NRHS;
@@ -398,11 +396,12 @@ __device__ __forceinline__ void sweep_tile(const SysDev& S, int32_t tile, const 
                 if (!BF && k0 + u >= w) continue;
 #pragma unroll
                 for (int c = 0; c < NRHS; ++c) q[c] = fmaT(a[u], xv[u][c], q[c]);
-                // the stored diagonal is nonzero; padding slots hold 0.  With
-                // four right-hand sides a shift table's diagonal is found as
-                // its slot of shift self - i (the same for every row of the
-                // tile), so that the gathered columns need not stay live:
-                // that keeps the sweep within 128 registers, 4 waves per SIMD
+                // the stored diagonal is nonzero; padding slots hold 0.  In
+                // FP64 a shift table's diagonal is found as its slot of shift
+                // self - i (the same for every row of the tile), so that the
+                // gathered columns need not stay live (with four right-hand
+                // sides that keeps the sweep within 128 registers, 4 waves per
+                // SIMD)
                 bool diag;
                 if constexpr (TAB && PREB) diag = shift[sbase + min(k0 + u, w - 1)] == self - i;
                 else diag = col[u] == self;
