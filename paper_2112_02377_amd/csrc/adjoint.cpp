@@ -53,7 +53,7 @@ static void build_transpose(Handle& h)
     PlanParams prm;
     prm.tile_rows = h.opt.tile_rows;
     prm.staged = false;
-    prm.tables = false;                  // the reverse step reads explicit columns
+    prm.tables = h.opt.tables != 0;      // a shift table where it streams fewer bytes (stencils)
     h.tplan = make_plan(at, {0, n}, prm);
     // A's plan was built on the same permuted matrix: its slot of entry q
     std::vector<int32_t> mapT((size_t)h.tplan.slots, -1);
@@ -66,7 +66,8 @@ static void build_transpose(Handle& h)
     up(h.td.tile_row0, t.tile_row0.data(), t.tile_row0.size() * 4);
     up(h.td.tile_slice0, t.tile_slice0.data(), t.tile_slice0.size() * 4);
     up(h.td.slice_off, t.slice_off.data(), t.slice_off.size() * 8);
-    if (t.colfmt == COL_REL16) up(h.td.col16, t.col16.data(), t.col16.size() * 2);
+    if (t.colfmt == COL_TABG) up(h.td.shift, t.shift.data(), t.shift.size() * 4);
+    else if (t.colfmt == COL_REL16) up(h.td.col16, t.col16.data(), t.col16.size() * 2);
     else up(h.td.col32, t.col32.data(), t.col32.size() * 4);
     up(h.td.t_map, mapT.data(), mapT.size() * 4);
     h.td.val.alloc((size_t)t.slots * sizeof(double));
@@ -272,6 +273,7 @@ extern "C" jac_status jac_adjoint(jac_handle hp, int32_t K, int32_t ckpt, const 
         sT.slice_off = static_cast<const int64_t*>(h.td.slice_off.p);
         sT.col32 = static_cast<const int32_t*>(h.td.col32.p);
         sT.col16 = static_cast<const uint16_t*>(h.td.col16.p);
+        sT.shift = static_cast<const int32_t*>(h.td.shift.p);
         sT.val = h.td.val.p;
         sT.n = n;
         sT.ntiles = h.tplan.ntiles;

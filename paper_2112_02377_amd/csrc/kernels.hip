@@ -1225,6 +1225,8 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
     const gptr<const int32_t> col32 = (gptr<const int32_t>)S.col32;
     const gptr<const uint16_t> col16 = (gptr<const uint16_t>)S.col16;
     const gptr<const double> mu = (gptr<const double>)mu_;
+    const cptr<const int32_t> shift = (cptr<const int32_t>)S.shift;
+    const int32_t n = S.n;
     const cptr<const int32_t> tile_row0 = (cptr<const int32_t>)S.tile_row0;
     const cptr<const int32_t> tile_slice0 = (cptr<const int32_t>)S.tile_slice0;
     const cptr<const int64_t> slice_off = (cptr<const int64_t>)S.slice_off;
@@ -1257,10 +1259,18 @@ __global__ void __launch_bounds__(512) k_adj_step(const SysDev* sysT, const doub
                 double a[KB];
                 int32_t raw[KB];
                 load_batch<NT, double, CM>(val, col32, col16, off, k0, w, a, raw);
+                // a shift table's slot k is column i + shift[k] of every row
+                // of the slice (a zero where the row has none: the column is
+                // only clamped into range)
                 double mv[KB];
 #pragma unroll
                 for (int u = 0; u < KB; ++u)
-                    if (k0 + u < w) mv[u] = mu[(CM == COL_REL16) ? i + raw[u] : raw[u]];
+                    if (k0 + u < w) {
+                        int32_t j;
+                        if constexpr (CM == COL_TABG) j = min(max(i + shift[(soff >> 6) + k0 + u], 0), n - 1);
+                        else j = (CM == COL_REL16) ? i + raw[u] : raw[u];
+                        mv[u] = mu[j];
+                    }
 #pragma unroll
                 for (int u = 0; u < KB; ++u)
                     if (k0 + u < w) q = __builtin_fma(a[u], mv[u], q);
@@ -1371,8 +1381,13 @@ void launch_adj_step(int colfmt, bool keep, int ntiles, hipStream_t st, const Sy
                      const double* mu, double* lam_out, double* mu_out, double* gb, const double* invd)
 {
     const int g = std::max(ntiles, 1);
-    // global or row-relative columns only: tile-local offsets need the staged footprint
-    if (colfmt == COL_REL16 && keep)
+    // global or row-relative columns or a shift table: tile-local offsets
+    // need the staged footprint
+    if (colfmt == COL_TABG && keep)
+        k_adj_step<COL_TABG, false><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else if (colfmt == COL_TABG)
+        k_adj_step<COL_TABG, true><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
+    else if (colfmt == COL_REL16 && keep)
         k_adj_step<COL_REL16, false><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
     else if (colfmt == COL_REL16)
         k_adj_step<COL_REL16, true><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
@@ -1381,7 +1396,7 @@ void launch_adj_step(int colfmt, bool keep, int ntiles, hipStream_t st, const Sy
     else if (colfmt == COL_GLOBAL32)
         k_adj_step<COL_GLOBAL32, true><<<g, 256, 0, st>>>(sysT, lam_in, mu, lam_out, mu_out, gb, invd);
     else
-        fail(JAC_E_INVALID, "adjoint step needs global or row-relative columns");
+        fail(JAC_E_INVALID, "adjoint step needs global or row-relative columns or a shift table");
     JAC_HIP(hipGetLastError());
 }
 
